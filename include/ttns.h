@@ -1,0 +1,195 @@
+/*
+ * ttns.h -- C-ABI of the MI355X tree-tensor-network-state (TTNS) one-site
+ * TDVP library.
+ *
+ * What it computes.  The state of a system coupled to bosonic environments is
+ * a TTNS (paper: "TTNS for vibronic quantum dynamics"): one tensor per tree
+ * node, the electronic levels at the root, one node per chain site of the
+ * chain-mapped environments of Eq. (2), optionally entanglement-
+ * renormalisation (ER) nodes between the root and the chains (Fig. 2).  The
+ * Hamiltonian is given as an operator sum over nodes ("tree MPO").  A time
+ * step evolves every node with exp(-i h H_eff) and every bond matrix with
+ * exp(+i h H_bond), sequentially over the tree, where H_eff is rebuilt from
+ * the full state at every node visit (the time-dependent variational
+ * principle the paper uses; Methods, "Tensor Network States").  The local
+ * exponentials are Lanczos/Krylov approximations.
+ *
+ * Conventions.
+ *   - Complex numbers are ttns_c64 {re, im} (interleaved, like C99 double
+ *     complex).  Operator matrices are row-major, op[r * d + c].
+ *   - Nodes are numbered in pre-order: parent[0] = -1, parent[i] < i, and the
+ *     nodes of every subtree are contiguous.  Children are ordered by index.
+ *   - Node tensor axes: [bond to parent] (absent at the root), physical leg,
+ *     bonds to the children in child order; row-major, last axis fastest.
+ *   - Every call returns a status: TTNS_OK or a negative code.  No call
+ *     aborts; ttns_last_error() returns a message for the calling thread.
+ *   - Device pointers ("dev_") are HIP device addresses; host pointers are
+ *     ordinary memory.  The caller owns every buffer it passes; the library
+ *     copies host inputs during the call and never frees caller memory.
+ *   - Nothing in the library allocates device memory: all device state lives
+ *     in the workspace the caller passes to ttns_build.
+ */
+#ifndef TTNS_H
+#define TTNS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define TTNS_OK 0
+#define TTNS_EINVAL (-1)   /* invalid argument, topology or Hamiltonian   */
+#define TTNS_ENOMEM (-2)   /* workspace too small                          */
+#define TTNS_EDEVICE (-3)  /* a HIP call failed                             */
+#define TTNS_ENUMERIC (-4) /* NaN/Inf or norm watchdog tripped             */
+
+/* arithmetic of the H_eff contractions (Lanczos, exponentials, QR and the
+ * environments always run in FP64) */
+#define TTNS_FP64 0
+#define TTNS_FP32 1    /* contractions in FP32 with FP32 accumulation      */
+#define TTNS_BF16X3 2  /* split-BF16 (hi*hi + hi*lo + lo*hi), FP32 accum.  */
+
+/* executors */
+#define TTNS_EXEC_AUTO 0
+#define TTNS_EXEC_WIDE 1       /* each operation spread over many workgroups */
+#define TTNS_EXEC_PERSISTENT 2 /* one workgroup runs a whole tree's step     */
+
+/* observables (ttns_observe kinds) */
+#define TTNS_OBS_RDM 0       /* root reduced density matrix, n x n complex:
+                                2 n^2 doubles (re, im), row-major           */
+#define TTNS_OBS_POP 1       /* root populations rho_jj, n doubles           */
+#define TTNS_OBS_LOCAL 2     /* recorded local expectation values (n_observe) */
+#define TTNS_OBS_NORM 3      /* <psi|psi>, 1 double                          */
+#define TTNS_OBS_ENERGY 4    /* <psi|H|psi>, 1 double                        */
+#define TTNS_OBS_HISTORY 5   /* every record so far: records x record_size   */
+#define TTNS_OBS_RECORD_SIZE 6 /* doubles per record (1 double)              */
+#define TTNS_OBS_TENSOR 7    /* node tensor `index`, 2*size doubles          */
+#define TTNS_OBS_STATS 8     /* [records, guarded QR columns, steps]          */
+#define TTNS_OBS_BOND_DIMS 9 /* clamped bond dims, n_nodes doubles (0: root) */
+
+typedef struct {
+  double re, im;
+} ttns_c64;
+
+/* One operator-sum term: coef * op_a (at node_a) (x) op_b (at node_b).
+ * node_b = -1 marks an on-site term.  Hermitian conjugate pairs are listed
+ * explicitly by the caller (the sum must be Hermitian; ttns_build checks). */
+typedef struct {
+  int32_t node_a, op_a;
+  int32_t node_b, op_b;
+  double coef;
+} ttns_term;
+
+/* A tree, its Hamiltonian and its initial product state. */
+typedef struct {
+  int32_t n_nodes;
+  const int32_t *parent;     /* n_nodes, pre-order (see conventions)        */
+  const int32_t *phys_dim;   /* n_nodes, >= 1 (ER nodes: 1)                 */
+  const int32_t *bond_dim;   /* n_nodes, requested D of edge (i, parent[i]);
+                                clamped to what either side can carry       */
+  int32_t n_ops;
+  const int32_t *op_dim;     /* n_ops                                        */
+  const ttns_c64 *op_data;   /* the n_ops matrices, concatenated             */
+  int32_t n_terms;
+  const ttns_term *terms;
+  const ttns_c64 *init_local;/* phys_dim[i] amplitudes per node, in node order;
+                                node i's tensor starts as an isometry whose
+                                first column is init_local(i) (x) children's
+                                first states, completed by unit vectors     */
+  int32_t n_observe;         /* local operators recorded every step          */
+  const int32_t *observe_node;
+  const int32_t *observe_op;
+} ttns_tree;
+
+/* The star Hamiltonian of Eq. (2): an electronic system H_S coupled through
+ * operators A_i to bosonic environments with power-law spectral densities
+ * J_i(w) = 2 pi alpha_i wc_i (w/wc_i)^s_i theta(wc_i - w), each mapped to a
+ * chain of `length` sites (orthogonal-polynomial chain mapping, closed form).
+ * Built into a tree whose root carries H_S and whose chain sites carry
+ * eps_n b^+b and t_n (b_n^+ b_{n+1} + h.c.); the root couples to site 0 by
+ * A_i (x) c0_i (b_0 + b_0^+).  Head occupations <b_0^+ b_0> are recorded. */
+typedef struct {
+  int32_t n_levels;
+  const ttns_c64 *h_el;      /* n_levels^2                                   */
+  const ttns_c64 *init_el;   /* n_levels amplitudes; chains start in vacuum  */
+  int32_t n_chains;
+  const ttns_c64 *coupling;  /* n_chains * n_levels^2: A_i                   */
+  const double *alpha, *wc, *s;
+  const int32_t *length, *local_dim, *bond_dim;
+  int32_t topology;          /* 0: chains hang off the root; 1: binary tree
+                                of ER nodes between the root and the chains */
+  int32_t er_bond_dim;       /* D on root-ER and ER-ER edges                 */
+} ttns_star_model;
+
+typedef struct {
+  int32_t precision;         /* TTNS_FP64 / TTNS_FP32 / TTNS_BF16X3          */
+  int32_t krylov_dim;        /* Lanczos dimension m, 1..16 (default 12)      */
+  double breakdown_tol;      /* stop Lanczos at beta_j <= tol*|x| (1e-12)    */
+  double rank_tol;           /* QR completion below tol*|A|_F (1e-8)        */
+  int32_t record_capacity;   /* records kept on the device (>= 1)            */
+  int32_t executor;          /* TTNS_EXEC_*                                  */
+  uint32_t flags;            /* reserved, 0                                  */
+} ttns_opts;
+
+typedef struct ttns_ctx ttns_ctx;
+
+/* Fill opts with the defaults named above. */
+void ttns_default_opts(ttns_opts *opts);
+
+/* Chain mapping (closed form of the hard-cutoff power-law density, Chin et
+ * al. 2010 as cited by the paper): c0, eps[0..L-1], hop[0..L-2]. */
+int ttns_ohmic_chain(double alpha, double wc, double s, int32_t L, double *c0,
+                     double *eps, double *hop);
+
+/* Device bytes ttns_build needs for these trees (all trees run together). */
+int ttns_workspace_size(const ttns_tree *trees, int32_t n_trees,
+                        const ttns_opts *opts, size_t *bytes);
+int ttns_star_workspace_size(const ttns_star_model *models, int32_t n_models,
+                             const ttns_opts *opts, size_t *bytes);
+
+/* Validate, lay out the workspace, upload operators, initialise the padded
+ * product state and build every environment towards the root.  dev_ws must
+ * hold ws_bytes >= ttns_workspace_size(...) bytes, 256-byte aligned; it is
+ * used until ttns_destroy.  hip_stream (hipStream_t, may be NULL for the
+ * default stream) orders all device work of this context.  Records t = 0. */
+int ttns_build(const ttns_tree *trees, int32_t n_trees, const ttns_opts *opts,
+               void *dev_ws, size_t ws_bytes, void *hip_stream, ttns_ctx **out);
+int ttns_star_build(const ttns_star_model *models, int32_t n_models,
+                    const ttns_opts *opts, void *dev_ws, size_t ws_bytes,
+                    void *hip_stream, ttns_ctx **out);
+
+/* Move the orthogonality centre of `tree` to `node` (QR + environment
+ * updates, a gauge change only), then dev_out = H_eff(node) dev_in, where
+ * dev_in/dev_out hold one node tensor (complex, node tensor layout).  The
+ * centre stays at `node`; the next ttns_tdvp_step moves it back to the root.
+ * Asynchronous on the context's stream. */
+int ttns_apply_heff(ttns_ctx *ctx, int32_t tree, int32_t node,
+                    const void *dev_in, void *dev_out);
+
+/* n_steps second-order TDVP steps of size dt (Hamiltonian time units) on
+ * every tree: pre-order sweep with h = dt/2 then the adjoint post-order
+ * sweep; observables recorded after every step.  Asynchronous. */
+int ttns_tdvp_step(ttns_ctx *ctx, double dt, int32_t n_steps);
+
+/* Copy an observable to host memory (synchronises the stream).  n_out is the
+ * capacity of host_out in doubles; TTNS_EINVAL if too small. */
+int ttns_observe(ttns_ctx *ctx, int32_t kind, int32_t tree, int32_t index,
+                 double *host_out, size_t n_out);
+
+/* Average device time (ms) per launch of the H_eff contraction kernel over
+ * the launches timed since the last call with reset != 0 (events around
+ * every launch of that kernel; enabled by ttns_profile(ctx, 1)). */
+int ttns_profile(ttns_ctx *ctx, int32_t enable);
+int ttns_profile_read(ttns_ctx *ctx, int32_t reset, double *avg_ms,
+                      int64_t *launches, double *flops_per_launch);
+
+int ttns_destroy(ttns_ctx *ctx);
+const char *ttns_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TTNS_H */

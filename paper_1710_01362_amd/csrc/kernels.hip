@@ -1,0 +1,946 @@
+// Device code of the TTNS one-site TDVP step for gfx950 (CDNA4), FP64 path.
+//
+// Every operation of the sweep is a device function over "virtual
+// workgroups" (vb = 0 .. nvb-1) of kBlock threads:
+//   * the wide executor launches one kernel per operation with nvb real
+//     workgroups; operations that reduce across workgroups write per-vb
+//     partial sums and the last workgroup to finish (atomic ticket) folds
+//     them in vb order, so results are bitwise reproducible;
+//   * the persistent executor runs a whole tree's operation list inside one
+//     workgroup, looping vb and calling the same fold afterwards.
+//
+// Complex numbers are double2 (re, im).  No floating-point atomics anywhere.
+#include <hip/hip_runtime.h>
+
+#include "ttns_internal.h"
+
+namespace ttns {
+
+// ------------------------------------------------------------ complex helpers
+__device__ __forceinline__ cd cz() { return make_double2(0.0, 0.0); }
+__device__ __forceinline__ cd cadd(cd a, cd b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ cd csub(cd a, cd b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ cd cscale(cd a, double s) { return make_double2(a.x * s, a.y * s); }
+// c + a * b
+__device__ __forceinline__ cd cfma(cd a, cd b, cd c) {
+  return make_double2(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
+}
+// c + conj(a) * b
+__device__ __forceinline__ cd cjfma(cd a, cd b, cd c) {
+  return make_double2(fma(a.x, b.x, fma(a.y, b.y, c.x)), fma(a.x, b.y, fma(-a.y, b.x, c.y)));
+}
+__device__ __forceinline__ double cabs2(cd a) { return a.x * a.x + a.y * a.y; }
+
+// ------------------------------------------------------------ shared memory
+struct Smem {
+  cd red[kBlock / 64];
+  cd wred[kBlock / 64][kRedStride];  // per-wavefront partial sums
+  cd vec[kRedStride];          // broadcast scalars (dot products, coefficients)
+  cd M[kMaxKrylov * kMaxKrylov];  // Krylov exponential work
+  cd P[kMaxKrylov * kMaxKrylov];
+  cd Q[kMaxKrylov * kMaxKrylov];
+  int rowbase[1024];           // contraction: row -> tensor offset
+  int ival[4];
+  double dval[4];
+};
+
+// Sum over the workgroup in a fixed order (wave butterfly, then waves 0..3).
+__device__ cd block_sum(cd v, Smem& sm) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    v.x += __shfl_xor(v.x, off);
+    v.y += __shfl_xor(v.y, off);
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sm.red[wid] = v;
+  __syncthreads();
+  cd r = sm.red[0];
+#pragma unroll
+  for (int w = 1; w < kBlock / 64; ++w) r = cadd(r, sm.red[w]);
+  return r;
+}
+
+__device__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  return v;
+}
+
+// Atomic ticket: true in the workgroup that finishes last (wide executor).
+// Every thread releases its own writes before the barrier; the winner
+// acquires before it reads the other workgroups' partial results.
+__device__ bool last_block(unsigned* counter, int nvb, Smem& sm) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned prev = atomicAdd(counter, 1u);
+    sm.ival[0] = (prev == (unsigned)(nvb - 1));
+    if (sm.ival[0]) atomicExch(counter, 0u);
+  }
+  __syncthreads();
+  const bool last = sm.ival[0] != 0;
+  if (last) __threadfence();
+  return last;
+}
+
+// ------------------------------------------------------------ H_eff apply
+__device__ __forceinline__ int coord(const Shape& sh, int idx, int a) {
+  return (idx / sh.stride[a]) % sh.dims[a];
+}
+
+// One output element of y = site o x + sum_e coef_e op_e o E_e (src_e).
+__device__ cd apply_point(const ApplyDesc& d, const cd* __restrict__ x, int idx) {
+  const Shape& sh = d.sh;
+  const int pa = sh.phys_axis;
+  const int dp = sh.dims[pa], sp = sh.stride[pa];
+  const int s = coord(sh, idx, pa);
+  cd acc = cz();
+  if (d.site) {
+    const int lo = max(d.site_lo, -s), hi = min(d.site_hi, dp - 1 - s);
+    cd part = cz();
+    for (int o = lo; o <= hi; ++o) part = cfma(d.site[s * dp + s + o], x[idx + o * sp], part);
+    acc = cscale(part, d.site_coef);
+  }
+  for (int k = 0; k < d.n_entries; ++k) {
+    const Entry& e = d.e[k];
+    const cd* __restrict__ src = e.src < 0 ? x : d.tmp[e.src];
+    const int D = sh.dims[e.axis], st = sh.stride[e.axis];
+    const int a = coord(sh, idx, e.axis);
+    const int base = idx - a * st;
+    const cd* __restrict__ Erow = e.E + a * D;
+    cd part = cz();
+    if (!e.op) {
+      for (int b = 0; b < D; ++b) part = cfma(Erow[b], src[base + b * st], part);
+    } else {
+      const int lo = max(e.op_lo, -s), hi = min(e.op_hi, dp - 1 - s);
+      for (int o = lo; o <= hi; ++o) {
+        const cd oc = e.op[s * dp + s + o];
+        const cd* __restrict__ sb = src + base + o * sp;
+        cd inner = cz();
+        for (int b = 0; b < D; ++b) inner = cfma(Erow[b], sb[b * st], inner);
+        part = cfma(oc, inner, part);
+      }
+    }
+    acc.x = fma(e.coef, part.x, acc.x);
+    acc.y = fma(e.coef, part.y, acc.y);
+  }
+  return acc;
+}
+
+// OP_APPLY: desc.y = H x with x = op.p0 when given (Lanczos pre-stages read
+// the current Krylov vector), else desc.x.
+__device__ void body_apply(const Op& op, const DevTables& T, int vb) {
+  const ApplyDesc& d = T.descs[op.desc];
+  const cd* x = op.p0 ? op.p0 : d.x;
+  const int idx = vb * kBlock + threadIdx.x;
+  if (idx < d.sh.size) d.y[idx] = apply_point(d, x, idx);
+}
+
+// ------------------------------------------------------------ Lanczos pieces
+// Partial sums of conj(V_i) . w (i = 0..j) and |w|^2 of this vb: every
+// thread forms its j+2 products, each wavefront reduces them by butterflies,
+// and the four wavefront sums are added in order.
+__device__ void lz_partials(const TreeDev& tr, int j, int n, int vb, int idx, cd w, Smem& sm) {
+  constexpr int kChunk = 6;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int cnt = j + 2;
+  for (int c0 = 0; c0 < cnt; c0 += kChunk) {  // uniform trip count
+    cd val[kChunk];
+#pragma unroll
+    for (int q = 0; q < kChunk; ++q) {
+      const int i = c0 + q;
+      val[q] = cz();
+      if (idx < n) {
+        if (i <= j) val[q] = cjfma(tr.V[(size_t)i * tr.ldv + idx], w, val[q]);
+        else if (i == j + 1) val[q].x = cabs2(w);
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        val[q].x += __shfl_xor(val[q].x, off);
+        val[q].y += __shfl_xor(val[q].y, off);
+      }
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int q = 0; q < kChunk; ++q)
+        if (c0 + q < kRedStride) sm.wred[wid][c0 + q] = val[q];
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < cnt) {
+    cd s = sm.wred[0][threadIdx.x];
+#pragma unroll
+    for (int w2 = 1; w2 < kBlock / 64; ++w2) s = cadd(s, sm.wred[w2][threadIdx.x]);
+    tr.partials[vb * kRedStride + threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+// Fold partial sums into out[0..cnt-1] (the last one into *last when given).
+// Few workgroups: one thread per value, vb order.  Many: every thread sums a
+// strided share of the workgroups, then a fixed-order block reduction.
+__device__ void fold_partials(const TreeDev& tr, int nvb, int cnt, cd* out, double* last, Smem& sm) {
+  const int t = threadIdx.x;
+  if (nvb <= 64) {
+    if (t < cnt) {
+      cd s = cz();
+      for (int b = 0; b < nvb; ++b) s = cadd(s, tr.partials[b * kRedStride + t]);
+      if (t == cnt - 1 && last) *last = s.x;
+      else out[t] = s;
+    }
+    return;
+  }
+  for (int i = 0; i < cnt; ++i) {
+    cd s = cz();
+    for (int b = t; b < nvb; b += kBlock) s = cadd(s, tr.partials[b * kRedStride + i]);
+    s = block_sum(s, sm);
+    if (t == 0) {
+      if (i == cnt - 1 && last) *last = s.x;
+      else out[i] = s;
+    }
+  }
+}
+
+// OP_NORM: |x| of the vector about to be evolved (op.p0, op.n elements).
+__device__ void body_norm(const Op& op, const DevTables& T, int vb, Smem& sm) {
+  const TreeDev& tr = T.trees[op.tree];
+  const int idx = vb * kBlock + threadIdx.x;
+  cd q = make_double2(idx < op.n ? cabs2(op.p0[idx]) : 0.0, 0.0);
+  q = block_sum(q, sm);
+  if (threadIdx.x == 0) tr.partials[vb * kRedStride] = q;
+}
+__device__ void fin_norm(const Op& op, const DevTables& T, int nvb, Smem& sm) {
+  const TreeDev& tr = T.trees[op.tree];
+  cd part = cz();
+  for (int b = threadIdx.x; b < nvb; b += kBlock) part = cadd(part, tr.partials[b * kRedStride]);
+  const double s = block_sum(part, sm).x;
+  if (threadIdx.x == 0) {
+    const double nx = sqrt(s);
+    tr.scal->nx = nx;
+    tr.scal->inv_nx = nx > 0.0 ? 1.0 / nx : 0.0;
+    tr.scal->done = nx > 0.0 ? 0 : 1;
+    tr.scal->k_eff = 0;
+  }
+}
+
+// OP_SCALE: V_0 = x / |x|
+__device__ void body_scale(const Op& op, const DevTables& T, int vb) {
+  const TreeDev& tr = T.trees[op.tree];
+  const int idx = vb * kBlock + threadIdx.x;
+  if (idx < op.n) tr.V[idx] = cscale(op.p0[idx], tr.scal->inv_nx);
+}
+
+// OP_APPLY_LZ: W = H V_j and its partial dots.  Returns false when the
+// Lanczos process already stopped (uniform over all workgroups).
+__device__ bool body_apply_lz(const Op& op, const DevTables& T, int vb, Smem& sm) {
+  const TreeDev& tr = T.trees[op.tree];
+  if (tr.scal->done) return false;
+  const ApplyDesc& d = T.descs[op.desc];
+  const int n = d.sh.size;
+  const int idx = vb * kBlock + threadIdx.x;
+  cd w = cz();
+  if (idx < n) {
+    w = apply_point(d, tr.V + (size_t)op.j * tr.ldv, idx);
+    tr.W[idx] = w;
+  }
+  lz_partials(tr, op.j, n, vb, idx, w, sm);
+  return true;
+}
+__device__ void fin_apply_lz(const Op& op, const DevTables& T, int nvb, Smem& sm) {
+  const TreeDev& tr = T.trees[op.tree];
+  fold_partials(tr, nvb, op.j + 2, tr.scal->h1, &tr.scal->ww1, sm);
+}
+
+// OP_ORTH1: first classical Gram-Schmidt pass, partial dots of the result.
+__device__ bool body_orth1(const Op& op, const DevTables& T, int vb, Smem& sm) {
+  const TreeDev& tr = T.trees[op.tree];
+  if (tr.scal->done) return false;
+  const int n = op.n, j = op.j;
+  const int idx = vb * kBlock + threadIdx.x;
+  cd w = cz();
+  if (idx < n) {
+    w = tr.W[idx];
+    for (int i = 0; i <= j; ++i) {
+      const cd h = tr.scal->h1[i];
+      const cd v = tr.V[(size_t)i * tr.ldv + idx];
+      w = csub(w, make_double2(h.x * v.x - h.y * v.y, h.x * v.y + h.y * v.x));
+    }
+    tr.W[idx] = w;
+  }
+  lz_partials(tr, j, n, vb, idx, w, sm);
+  return true;
+}
+__device__ void fin_orth1(const Op& op, const DevTables& T, int nvb, Smem& sm) {
+  const TreeDev& tr = T.trees[op.tree];
+  fold_partials(tr, nvb, op.j + 2, tr.scal->h2, &tr.scal->ww2, sm);
+}
+
+// beta_j from the second pass (same value in every workgroup).
+__device__ double lz_beta(const LzScal* sc, int j) {
+  double b2 = sc->ww2;
+  for (int i = 0; i <= j; ++i) b2 -= cabs2(sc->h2[i]);
+  return sqrt(fmax(b2, 0.0));
+}
+
+// OP_ORTH2: second pass, beta_j, V_{j+1} (unless the process stops here).
+__device__ bool body_orth2(const Op& op, const DevTables& T, int vb) {
+  const TreeDev& tr = T.trees[op.tree];
+  const LzScal* sc = tr.scal;
+  if (sc->done) return false;
+  const int n = op.n, j = op.j;
+  const double beta = lz_beta(sc, j);
+  const bool stop = (j == tr.kmax - 1) || (j == n - 1) || (beta <= tr.btol * sc->nx);
+  if (stop) return true;
+  const double ib = 1.0 / beta;
+  const int idx = vb * kBlock + threadIdx.x;
+  if (idx < n) {
+    cd w = tr.W[idx];
+    for (int i = 0; i <= j; ++i) {
+      const cd h = sc->h2[i];
+      const cd v = tr.V[(size_t)i * tr.ldv + idx];
+      w = csub(w, make_double2(h.x * v.x - h.y * v.y, h.x * v.y + h.y * v.x));
+    }
+    tr.V[(size_t)(j + 1) * tr.ldv + idx] = cscale(w, ib);
+  }
+  return true;
+}
+__device__ void fin_orth2(const Op& op, const DevTables& T) {
+  const TreeDev& tr = T.trees[op.tree];
+  LzScal* sc = tr.scal;
+  if (threadIdx.x == 0) {
+    const int j = op.j;
+    const double beta = lz_beta(sc, j);
+    sc->alpha[j] = sc->h1[j].x + sc->h2[j].x;
+    const bool stop = (j == tr.kmax - 1) || (j == op.n - 1) || (beta <= tr.btol * sc->nx);
+    if (stop) {
+      sc->k_eff = j + 1;
+      sc->done = 1;
+      if (j < tr.kmax - 1 && j < op.n - 1) atomicAdd(&tr.stats[1], 1);
+    } else {
+      sc->beta[j] = beta;
+    }
+  }
+}
+
+// exp(i zim T) e_1 for the k x k real symmetric tridiagonal T = (alpha,
+// beta): scaling and squaring with an 18-term Taylor series of the scaled
+// matrix (|i zim T / 2^q| <= 1/2).  Result in sm.vec[0..k-1]; all threads.
+__device__ void krylov_exp(const double* alpha, const double* beta, int k, double zim, Smem& sm) {
+  const int t = threadIdx.x;
+  if (t < 64) {
+    double nb = 0.0;
+    if (t < k) {
+      nb = fabs(alpha[t]);
+      if (t > 0) nb += fabs(beta[t - 1]);
+      if (t + 1 < k) nb += fabs(beta[t]);
+    }
+    nb = wave_max(nb) * fabs(zim);
+    if (t == 0) {
+      int q = 0;
+      double sc = 1.0;
+      while (nb * sc > 0.5 && q < 60) {
+        sc *= 0.5;
+        ++q;
+      }
+      sm.ival[1] = q;
+      sm.dval[0] = sc;
+    }
+  }
+  __syncthreads();
+  const int q = sm.ival[1];
+  const double zs = zim * sm.dval[0];
+  const int r = t / kMaxKrylov, c = t % kMaxKrylov;
+  const bool mine = (t < kMaxKrylov * kMaxKrylov) && r < k && c < k;
+  // P = I, M = I
+  if (t < kMaxKrylov * kMaxKrylov) {
+    cd one = make_double2((r == c) ? 1.0 : 0.0, 0.0);
+    sm.P[t] = one;
+    sm.M[t] = one;
+  }
+  __syncthreads();
+  for (int term = 1; term <= 18; ++term) {
+    // P <- P (i zs T) / term
+    cd v = cz();
+    if (mine) {
+      cd acc = cz();
+      if (c > 0) acc = cscale(sm.P[r * kMaxKrylov + c - 1], beta[c - 1]);
+      acc = cadd(acc, cscale(sm.P[r * kMaxKrylov + c], alpha[c]));
+      if (c + 1 < k) acc = cadd(acc, cscale(sm.P[r * kMaxKrylov + c + 1], beta[c]));
+      const double f = zs / (double)term;
+      v = make_double2(-acc.y * f, acc.x * f);  // i * f * acc
+    }
+    __syncthreads();
+    if (mine) {
+      sm.P[r * kMaxKrylov + c] = v;
+      sm.M[r * kMaxKrylov + c] = cadd(sm.M[r * kMaxKrylov + c], v);
+    }
+    __syncthreads();
+  }
+  for (int sq = 0; sq < q; ++sq) {
+    cd v = cz();
+    if (mine)
+      for (int m = 0; m < k; ++m) v = cfma(sm.M[r * kMaxKrylov + m], sm.M[m * kMaxKrylov + c], v);
+    __syncthreads();
+    if (mine) sm.M[r * kMaxKrylov + c] = v;
+    __syncthreads();
+  }
+  if (t < k) sm.vec[t] = sm.M[t * kMaxKrylov];
+  __syncthreads();
+}
+
+// OP_COMBINE: out = |x| sum_i c_i V_i with c = exp(sign i h T) e_1.
+__device__ void body_combine(const Op& op, const DevTables& T, int vb, Smem& sm) {
+  const TreeDev& tr = T.trees[op.tree];
+  const LzScal* sc = tr.scal;
+  const int k = sc->k_eff;
+  const double h = *T.half_step;
+  if (k > 0) krylov_exp(sc->alpha, sc->beta, k, op.sign * h, sm);
+  const int idx = vb * kBlock + threadIdx.x;
+  if (idx < op.n) {
+    cd acc = cz();
+    for (int i = 0; i < k; ++i) acc = cfma(sm.vec[i], tr.V[(size_t)i * tr.ldv + idx], acc);
+    op.p1[idx] = cscale(acc, sc->nx);
+  }
+}
+
+// ------------------------------------------------------------ guarded QR
+// Row r of the matricisation towards `ax` (other axes row-major in axis
+// order) -> tensor offset with column 0.
+__device__ int qr_row_offset(const Shape& sh, int ax, int r) {
+  int off = 0;
+  for (int a = sh.rank - 1; a >= 0; --a) {
+    if (a == ax) continue;
+    const int c = r % sh.dims[a];
+    r /= sh.dims[a];
+    off += c * sh.stride[a];
+  }
+  return off;
+}
+
+// Completion candidate n (physical index fastest, then the other bond axes
+// in axis order) -> row index of the matricisation towards `ax`.
+__device__ int qr_candidate_row(const Shape& sh, int ax, int n) {
+  int row = 0;
+  // row-major stride of axis a among the rows = product of later non-ax dims
+  auto rstride = [&](int a) {
+    int s = 1;
+    for (int b = a + 1; b < sh.rank; ++b)
+      if (b != ax) s *= sh.dims[b];
+    return s;
+  };
+  const int pa = sh.phys_axis;
+  if (pa != ax) {
+    row += (n % sh.dims[pa]) * rstride(pa);
+    n /= sh.dims[pa];
+  }
+  for (int a = 0; a < sh.rank; ++a) {
+    if (a == ax || a == pa) continue;
+    row += (n % sh.dims[a]) * rstride(a);
+    n /= sh.dims[a];
+  }
+  return row;
+}
+
+// h[j] = sum_r conj(Q_j[r]) v[r] for j < k (waves take columns, lanes rows).
+__device__ void qr_project(const cd* Q, const cd* v, int rows, int k, cd* h) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int j = wid; j < k; j += kBlock / 64) {
+    const cd* q = Q + (size_t)j * rows;
+    cd acc = cz();
+    for (int r = lane; r < rows; r += 64) acc = cjfma(q[r], v[r], acc);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      acc.x += __shfl_xor(acc.x, off);
+      acc.y += __shfl_xor(acc.y, off);
+    }
+    if (lane == 0) h[j] = acc;
+  }
+  __syncthreads();
+}
+
+// v[r] -= sum_j Q_j[r] h[j]; returns this thread's share of |v|^2.
+__device__ double qr_subtract(const cd* Q, cd* v, int rows, int k, const cd* h) {
+  double n2 = 0.0;
+  for (int r = threadIdx.x; r < rows; r += kBlock) {
+    cd acc = v[r];
+    for (int j = 0; j < k; ++j) {
+      const cd q = Q[(size_t)j * rows + r];
+      const cd hj = h[j];
+      acc = csub(acc, make_double2(q.x * hj.x - q.y * hj.y, q.x * hj.y + q.y * hj.x));
+    }
+    v[r] = acc;
+    n2 += cabs2(acc);
+  }
+  __syncthreads();
+  return n2;
+}
+
+// LDS budget of the QR (complex entries): Q columns plus two row vectors.
+constexpr int kQrLds = 8800;  // 137.5 KiB: a 400 x 20 matrix plus two vectors
+
+// OP_QR (one workgroup): node tensor op.p1 (shape of desc op.desc) = Q R
+// towards axis op.axis; Q overwrites the tensor, R -> tree R buffer.
+// Column-by-column classical Gram-Schmidt applied twice; a column whose
+// residual is <= rank_tol |A|_F is replaced by the first unit vector (in
+// completion order) farther than half the average from the span so far,
+// orthogonalised twice.  Q and the work vectors live in LDS (`lds`, kQrLds
+// entries) when they fit, else in the tree's global scratch.
+__device__ void body_qr(const Op& op, const DevTables& T, Smem& sm, cd* lds) {
+  const TreeDev& tr = T.trees[op.tree];
+  const Shape& sh = T.descs[op.desc].sh;
+  const int ax = op.axis;
+  const int cols = sh.dims[ax];
+  const int rows = sh.size / cols;
+  const int cst = sh.stride[ax];
+  const bool in_lds = (size_t)rows * (cols + 2) <= (size_t)kQrLds;
+  cd* A = tr.qrA;
+  cd* Q = in_lds ? lds : tr.qrQ;
+  cd* v = in_lds ? lds + (size_t)rows * cols : tr.qrv;
+  cd* u = in_lds ? v + rows : tr.qrv + tr.max_rows;
+  cd* R = tr.R;
+  cd* X = op.p1;
+  cd* h1 = sm.vec + 0;  // kRedStride >= 18; two halves of 64 below
+  __shared__ cd hb1[64], hb2[64];
+  (void)h1;
+  // gather A (column-major) and |A|_F^2
+  double nrm = 0.0;
+  for (int r = threadIdx.x; r < rows; r += kBlock) {
+    const int off = qr_row_offset(sh, ax, r);
+    for (int c = 0; c < cols; ++c) {
+      const cd a = X[off + c * cst];
+      A[(size_t)c * rows + r] = a;
+      nrm += cabs2(a);
+    }
+  }
+  for (int i = threadIdx.x; i < cols * cols; i += kBlock) R[i] = cz();
+  nrm = block_sum(make_double2(nrm, 0.0), sm).x;
+  const double tol = tr.rtol * sqrt(nrm);
+  for (int k = 0; k < cols; ++k) {
+    const cd* a = A + (size_t)k * rows;
+    for (int r = threadIdx.x; r < rows; r += kBlock) v[r] = a[r];
+    __syncthreads();
+    qr_project(Q, v, rows, k, hb1);
+    qr_subtract(Q, v, rows, k, hb1);
+    qr_project(Q, v, rows, k, hb2);
+    const double rn = sqrt(block_sum(make_double2(qr_subtract(Q, v, rows, k, hb2), 0.0), sm).x);
+    for (int j = threadIdx.x; j < k; j += kBlock) R[j * cols + k] = cadd(hb1[j], hb2[j]);
+    cd* qk = Q + (size_t)k * rows;
+    if (rn > tol) {
+      const double ir = 1.0 / rn;
+      for (int r = threadIdx.x; r < rows; r += kBlock) qk[r] = cscale(v[r], ir);
+      if (threadIdx.x == 0) R[k * cols + k] = make_double2(rn, 0.0);
+      __syncthreads();
+      continue;
+    }
+    // completion: first candidate with distance^2 > (rows - k) / (2 rows)
+    const double thr = 0.5 * (double)(rows - k) / (double)rows;
+    if (threadIdx.x < 64) {
+      int chosen = -1;
+      for (int base = 0; base < rows && chosen < 0; base += 64) {
+        const int n = base + (int)threadIdx.x;
+        bool ok = false;
+        if (n < rows) {
+          const int row = qr_candidate_row(sh, ax, n);
+          double s = 0.0;
+          for (int j = 0; j < k; ++j) s += cabs2(Q[(size_t)j * rows + row]);
+          ok = (1.0 - s) > thr;
+        }
+        const unsigned long long m = __ballot(ok);
+        if (m) chosen = base + __ffsll((long long)m) - 1;
+      }
+      if (threadIdx.x == 0) sm.ival[2] = chosen < 0 ? -1 : qr_candidate_row(sh, ax, chosen);
+    }
+    __syncthreads();
+    const int row = sm.ival[2];
+    if (row < 0) {
+      if (threadIdx.x == 0) atomicOr(&tr.stats[3], 1);  // cannot happen for rows >= cols
+      return;
+    }
+    // u = e_row - Q (Q^H e_row), then a second pass
+    for (int j = threadIdx.x; j < k; j += kBlock) {
+      const cd q = Q[(size_t)j * rows + row];
+      hb1[j] = make_double2(q.x, -q.y);
+    }
+    for (int r = threadIdx.x; r < rows; r += kBlock) u[r] = make_double2(r == row ? 1.0 : 0.0, 0.0);
+    __syncthreads();
+    qr_subtract(Q, u, rows, k, hb1);
+    qr_project(Q, u, rows, k, hb2);
+    const double iu = 1.0 / sqrt(block_sum(make_double2(qr_subtract(Q, u, rows, k, hb2), 0.0), sm).x);
+    cd rkk = cz();
+    for (int r = threadIdx.x; r < rows; r += kBlock) {
+      const cd q = cscale(u[r], iu);
+      qk[r] = q;
+      rkk = cjfma(q, v[r], rkk);
+    }
+    rkk = block_sum(rkk, sm);
+    if (threadIdx.x == 0) {
+      R[k * cols + k] = rkk;
+      atomicAdd(&tr.stats[0], 1);
+    }
+    __syncthreads();
+  }
+  // scatter Q back into the node tensor
+  for (int r = threadIdx.x; r < rows; r += kBlock) {
+    const int off = qr_row_offset(sh, ax, r);
+    for (int c = 0; c < cols; ++c) X[off + c * cst] = Q[(size_t)c * rows + r];
+  }
+}
+
+// ------------------------------------------------------------ contraction
+// OP_CONTRACT: E[a', a] = sum_r conj(Qm[r, a']) Zm[r, a] over the rows of
+// the matricisations towards op.axis; Q = op.p0, Z = op.p2, shape from
+// desc.  Output op.p1 (D x D, row-major) or, with op.i0 = 1, transposed
+// into the current record at double offset op.i1.  Rows are split over vb.
+__device__ void body_contract(const Op& op, const DevTables& T, int vb, Smem& sm) {
+  const TreeDev& tr = T.trees[op.tree];
+  const Shape& sh = T.descs[op.desc].sh;
+  const int ax = op.axis;
+  const int D = sh.dims[ax], st = sh.stride[ax];
+  const int rows = sh.size / D;
+  const int chunk = (rows + op.nvb - 1) / op.nvb;
+  const int r0 = vb * chunk, r1 = min(rows, r0 + chunk);
+  cd* part = tr.cpart + (size_t)vb * D * D;  // per-vb partial matrix
+  for (int p = threadIdx.x; p < D * D; p += kBlock) part[p] = cz();
+  for (int base = r0; base < r1; base += 1024) {
+    const int nb = min(1024, r1 - base);
+    __syncthreads();
+    for (int i = threadIdx.x; i < nb; i += kBlock) sm.rowbase[i] = qr_row_offset(sh, ax, base + i);
+    __syncthreads();
+    for (int p = threadIdx.x; p < D * D; p += kBlock) {
+      const int a1 = p / D, a2 = p % D;
+      cd acc = part[p];
+      for (int i = 0; i < nb; ++i) {
+        const int off = sm.rowbase[i];
+        acc = cjfma(op.p0[off + a1 * st], op.p2[off + a2 * st], acc);
+      }
+      part[p] = acc;
+    }
+  }
+}
+__device__ void fin_contract(const Op& op, const DevTables& T, int nvb) {
+  const TreeDev& tr = T.trees[op.tree];
+  const Shape& sh = T.descs[op.desc].sh;
+  const int D = sh.dims[op.axis];
+  for (int p = threadIdx.x; p < D * D; p += kBlock) {
+    cd s = cz();
+    for (int b = 0; b < nvb; ++b) s = cadd(s, tr.cpart[(size_t)b * D * D + p]);
+    if (op.i0 == 0) {
+      op.p1[p] = s;
+    } else {
+      const int slot = min(*tr.rec_count, tr.rec_cap - 1);
+      double* rec = tr.hist + (size_t)slot * tr.rec_size + op.i1;
+      const int a1 = p / D, a2 = p % D;
+      rec[2 * (a2 * D + a1)] = s.x;
+      rec[2 * (a2 * D + a1) + 1] = s.y;
+    }
+  }
+}
+
+// ------------------------------------------------------------ bond step
+// Y = H_b X for the bond matrix X (Du x Dv), one workgroup; scratch S (Du x Dv).
+__device__ void bond_apply(const BondDesc& b, const cd* X, cd* Y, cd* S) {
+  const int Du = b.Du, Dv = b.Dv, n = Du * Dv;
+  for (int p = threadIdx.x; p < n; p += kBlock) {
+    const int a = p / Dv, c = p % Dv;
+    cd acc = cz();
+    for (int m = 0; m < Du; ++m) acc = cfma(b.Eu[a * Du + m], X[m * Dv + c], acc);
+    for (int m = 0; m < Dv; ++m) acc = cfma(X[a * Dv + m], b.Ev[c * Dv + m], acc);
+    Y[p] = acc;
+  }
+  __syncthreads();
+  for (int k = 0; k < b.n_pairs; ++k) {
+    for (int p = threadIdx.x; p < n; p += kBlock) {
+      const int a = p / Dv, c = p % Dv;
+      cd acc = cz();
+      for (int m = 0; m < Dv; ++m) acc = cfma(X[a * Dv + m], b.Evk[k][c * Dv + m], acc);
+      S[p] = acc;
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < n; p += kBlock) {
+      const int a = p / Dv, c = p % Dv;
+      cd acc = cz();
+      for (int m = 0; m < Du; ++m) acc = cfma(b.Euk[k][a * Du + m], S[m * Dv + c], acc);
+      Y[p] = make_double2(fma(b.coef[k], acc.x, Y[p].x), fma(b.coef[k], acc.y, Y[p].y));
+    }
+    __syncthreads();
+  }
+}
+
+// OP_BOND (one workgroup): R <- exp(sign i h H_b) R by the same Lanczos
+// process as the nodes (CGS2, breakdown, Krylov dimension kmax).
+__device__ void body_bond(const Op& op, const DevTables& T, Smem& sm) {
+  const TreeDev& tr = T.trees[op.tree];
+  const BondDesc& b = T.bonds[op.desc];
+  const int n = b.Du * b.Dv;
+  const int ld = op.i0;  // leading dimension of the bond Krylov basis
+  cd* V = tr.bondV;
+  cd* W = tr.bondW;
+  cd* S = tr.bondW + ld;
+  __shared__ double al[kMaxKrylov], be[kMaxKrylov];
+  __shared__ cd hh[kRedStride];
+  cd q = cz();
+  for (int p = threadIdx.x; p < n; p += kBlock) q.x += cabs2(b.R[p]);
+  q = block_sum(q, sm);
+  const double nx = sqrt(q.x);
+  if (nx == 0.0) return;
+  const double inx = 1.0 / nx;
+  for (int p = threadIdx.x; p < n; p += kBlock) V[p] = cscale(b.R[p], inx);
+  __syncthreads();
+  const int kmax = min(tr.kmax, n);
+  int k = 0;
+  for (int j = 0; j < kmax; ++j) {
+    bond_apply(b, V + (size_t)j * ld, W, S);
+    double a_j = 0.0, ww = 0.0;
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int i = 0; i <= j; ++i) {
+        cd d = cz();
+        for (int p = threadIdx.x; p < n; p += kBlock) d = cjfma(V[(size_t)i * ld + p], W[p], d);
+        d = block_sum(d, sm);
+        if (threadIdx.x == 0) hh[i] = d;
+      }
+      __syncthreads();
+      for (int p = threadIdx.x; p < n; p += kBlock) {
+        cd w = W[p];
+        for (int i = 0; i <= j; ++i) {
+          const cd h = hh[i];
+          const cd v = V[(size_t)i * ld + p];
+          w = csub(w, make_double2(h.x * v.x - h.y * v.y, h.x * v.y + h.y * v.x));
+        }
+        W[p] = w;
+      }
+      a_j += hh[j].x;
+      __syncthreads();
+    }
+    cd nw = cz();
+    for (int p = threadIdx.x; p < n; p += kBlock) nw.x += cabs2(W[p]);
+    nw = block_sum(nw, sm);
+    ww = sqrt(nw.x);
+    if (threadIdx.x == 0) al[j] = a_j;
+    k = j + 1;
+    if (j == kmax - 1) break;
+    if (ww <= tr.btol * nx) {
+      if (threadIdx.x == 0) atomicAdd(&tr.stats[1], 1);
+      break;
+    }
+    if (threadIdx.x == 0) be[j] = ww;
+    const double iw = 1.0 / ww;
+    for (int p = threadIdx.x; p < n; p += kBlock) V[(size_t)(j + 1) * ld + p] = cscale(W[p], iw);
+    __syncthreads();
+  }
+  __syncthreads();
+  krylov_exp(al, be, k, op.sign * (*T.half_step), sm);
+  for (int p = threadIdx.x; p < n; p += kBlock) {
+    cd acc = cz();
+    for (int i = 0; i < k; ++i) acc = cfma(sm.vec[i], V[(size_t)i * ld + p], acc);
+    b.R[p] = cscale(acc, nx);
+  }
+}
+
+// ------------------------------------------------------------ small ops
+__device__ void body_copy(const Op& op, int vb) {
+  const int idx = vb * kBlock + threadIdx.x;
+  if (idx < op.n) op.p1[idx] = op.p0[idx];
+}
+
+// OP_DOT: Re <p0|p2> -> current record at double offset op.i1.
+__device__ void body_dot(const Op& op, const DevTables& T, int vb, Smem& sm) {
+  const TreeDev& tr = T.trees[op.tree];
+  const int idx = vb * kBlock + threadIdx.x;
+  cd p = cz();
+  if (idx < op.n) p = cjfma(op.p0[idx], op.p2[idx], p);
+  p = block_sum(p, sm);
+  if (threadIdx.x == 0) tr.partials[vb * kRedStride] = p;
+}
+__device__ void fin_dot(const Op& op, const DevTables& T, int nvb, Smem& sm) {
+  const TreeDev& tr = T.trees[op.tree];
+  cd part = cz();
+  for (int b = threadIdx.x; b < nvb; b += kBlock) part = cadd(part, tr.partials[b * kRedStride]);
+  const double s = block_sum(part, sm).x;
+  if (threadIdx.x == 0) {
+    const int slot = min(*tr.rec_count, tr.rec_cap - 1);
+    tr.hist[(size_t)slot * tr.rec_size + op.i1] = s;
+  }
+}
+
+// OP_RECORD: norm = trace of the recorded density matrix (op.i0 levels,
+// stored at offset 0, norm at offset op.i1); advance the record counter.
+__device__ void body_record(const Op& op, const DevTables& T) {
+  const TreeDev& tr = T.trees[op.tree];
+  if (threadIdx.x == 0) {
+    const int slot = min(*tr.rec_count, tr.rec_cap - 1);
+    double* rec = tr.hist + (size_t)slot * tr.rec_size;
+    double s = 0.0;
+    for (int j = 0; j < op.i0; ++j) s += rec[2 * (j * op.i0 + j)];
+    rec[op.i1] = s;
+    if (!isfinite(s)) atomicOr(&tr.stats[3], 2);
+    *tr.rec_count = min(*tr.rec_count + 1, tr.rec_cap);
+    if (op.j) tr.stats[2] += 1;
+  }
+}
+
+// ------------------------------------------------------------ executors
+template <int TY>
+__global__ __launch_bounds__(kBlock) void k_op(Op op, DevTables T) {
+  __shared__ Smem sm;
+  const int vb = blockIdx.x;
+  if constexpr (TY == OP_SETH) {
+    if (threadIdx.x == 0) *T.half_step = op.d0;
+    return;
+  }
+  const TreeDev& tr = T.trees[op.tree];
+  if constexpr (TY == OP_APPLY) {
+    body_apply(op, T, vb);
+  } else if constexpr (TY == OP_APPLY_LZ) {
+    if (body_apply_lz(op, T, vb, sm) && last_block(tr.counter, op.nvb, sm)) fin_apply_lz(op, T, op.nvb, sm);
+  } else if constexpr (TY == OP_NORM) {
+    body_norm(op, T, vb, sm);
+    if (last_block(tr.counter, op.nvb, sm)) fin_norm(op, T, op.nvb, sm);
+  } else if constexpr (TY == OP_SCALE) {
+    body_scale(op, T, vb);
+  } else if constexpr (TY == OP_ORTH1) {
+    if (body_orth1(op, T, vb, sm) && last_block(tr.counter, op.nvb, sm)) fin_orth1(op, T, op.nvb, sm);
+  } else if constexpr (TY == OP_ORTH2) {
+    if (body_orth2(op, T, vb) && last_block(tr.counter, op.nvb, sm)) fin_orth2(op, T);
+  } else if constexpr (TY == OP_COMBINE) {
+    body_combine(op, T, vb, sm);
+  } else if constexpr (TY == OP_QR) {
+    __shared__ cd qr_lds[kQrLds];
+    body_qr(op, T, sm, qr_lds);
+  } else if constexpr (TY == OP_CONTRACT) {
+    body_contract(op, T, vb, sm);
+    if (last_block(tr.counter, op.nvb, sm)) fin_contract(op, T, op.nvb);
+  } else if constexpr (TY == OP_BOND) {
+    body_bond(op, T, sm);
+  } else if constexpr (TY == OP_COPY) {
+    body_copy(op, vb);
+  } else if constexpr (TY == OP_DOT) {
+    body_dot(op, T, vb, sm);
+    if (last_block(tr.counter, op.nvb, sm)) fin_dot(op, T, op.nvb, sm);
+  } else if constexpr (TY == OP_RECORD) {
+    body_record(op, T);
+  }
+}
+
+// One workgroup runs the operation list of one tree: ops[begin[b], end[b]).
+__global__ __launch_bounds__(kBlock) void k_persistent(const Op* __restrict__ ops,
+                                                       const int* __restrict__ begin,
+                                                       const int* __restrict__ end, DevTables T) {
+  __shared__ Smem sm;
+  __shared__ cd qr_lds[kQrLds];
+  const int b = blockIdx.x;
+  for (int i = begin[b]; i < end[b]; ++i) {
+    const Op op = ops[i];
+    const int nvb = op.nvb;
+    switch (op.type) {
+      case OP_APPLY:
+        for (int vb = 0; vb < nvb; ++vb) body_apply(op, T, vb);
+        break;
+      case OP_APPLY_LZ: {
+        bool act = true;
+        for (int vb = 0; vb < nvb && act; ++vb) act = body_apply_lz(op, T, vb, sm);
+        __syncthreads();
+        if (act) fin_apply_lz(op, T, nvb, sm);
+        break;
+      }
+      case OP_NORM:
+        for (int vb = 0; vb < nvb; ++vb) body_norm(op, T, vb, sm);
+        __syncthreads();
+        fin_norm(op, T, nvb, sm);
+        break;
+      case OP_SCALE:
+        for (int vb = 0; vb < nvb; ++vb) body_scale(op, T, vb);
+        break;
+      case OP_ORTH1: {
+        bool act = true;
+        for (int vb = 0; vb < nvb && act; ++vb) act = body_orth1(op, T, vb, sm);
+        __syncthreads();
+        if (act) fin_orth1(op, T, nvb, sm);
+        break;
+      }
+      case OP_ORTH2: {
+        bool act = true;
+        for (int vb = 0; vb < nvb && act; ++vb) act = body_orth2(op, T, vb);
+        __syncthreads();
+        if (act) fin_orth2(op, T);
+        break;
+      }
+      case OP_COMBINE:
+        for (int vb = 0; vb < nvb; ++vb) body_combine(op, T, vb, sm);
+        break;
+      case OP_QR:
+        body_qr(op, T, sm, qr_lds);
+        break;
+      case OP_CONTRACT:
+        for (int vb = 0; vb < nvb; ++vb) body_contract(op, T, vb, sm);
+        __syncthreads();
+        fin_contract(op, T, nvb);
+        break;
+      case OP_BOND:
+        body_bond(op, T, sm);
+        break;
+      case OP_COPY:
+        for (int vb = 0; vb < nvb; ++vb) body_copy(op, vb);
+        break;
+      case OP_DOT:
+        for (int vb = 0; vb < nvb; ++vb) body_dot(op, T, vb, sm);
+        __syncthreads();
+        fin_dot(op, T, nvb, sm);
+        break;
+      case OP_RECORD:
+        body_record(op, T);
+        break;
+      default:
+        break;
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_op(const Op& op, const DevTables& t, hipStream_t s) {
+  const dim3 grid(op.nvb > 0 ? op.nvb : 1), block(kBlock);
+  switch (op.type) {
+#define TTNS_CASE(T_)                                            \
+  case T_:                                                       \
+    hipLaunchKernelGGL(k_op<T_>, grid, block, 0, s, op, t);      \
+    break;
+    TTNS_CASE(OP_APPLY)
+    TTNS_CASE(OP_APPLY_LZ)
+    TTNS_CASE(OP_NORM)
+    TTNS_CASE(OP_SCALE)
+    TTNS_CASE(OP_ORTH1)
+    TTNS_CASE(OP_ORTH2)
+    TTNS_CASE(OP_COMBINE)
+    TTNS_CASE(OP_QR)
+    TTNS_CASE(OP_CONTRACT)
+    TTNS_CASE(OP_BOND)
+    TTNS_CASE(OP_COPY)
+    TTNS_CASE(OP_DOT)
+    TTNS_CASE(OP_RECORD)
+    TTNS_CASE(OP_SETH)
+#undef TTNS_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_persistent(const Op* dev_ops, const int* dev_begin, const int* dev_end,
+                             int n_trees, const DevTables& t, hipStream_t s) {
+  hipLaunchKernelGGL(k_persistent, dim3(n_trees), dim3(kBlock), 0, s, dev_ops, dev_begin,
+                     dev_end, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_half_step(double* dst, double h, hipStream_t s) {
+  Op op{};
+  op.type = OP_SETH;
+  op.nvb = 1;
+  op.d0 = h;
+  DevTables t{};
+  t.half_step = dst;
+  hipLaunchKernelGGL(k_op<OP_SETH>, dim3(1), dim3(kBlock), 0, s, op, t);
+  return hipGetLastError();
+}
+
+}  // namespace ttns
