@@ -69,6 +69,8 @@ extern "C" {
 #define TTNS_OBS_TENSOR 7    /* node tensor `index`, 2*size doubles          */
 #define TTNS_OBS_STATS 8     /* [records, guarded QR columns, steps]          */
 #define TTNS_OBS_BOND_DIMS 9 /* clamped bond dims, n_nodes doubles (0: root) */
+#define TTNS_OBS_STEP_FLOPS 10 /* algorithmic real flops of one step of this
+                                  tree: [total, H_eff contractions only]     */
 
 typedef struct {
   double re, im;

@@ -36,6 +36,7 @@ int fail(int code, const std::string& msg) {
 constexpr int PHYS = -1;
 constexpr int kMaxD = 64;       // QR keeps per-column scalars in shared arrays
 constexpr int kMaxContractVb = 64;
+constexpr int kMfmaMinSize = 16384;  // FP64 nodes this large use the matrix cores
 
 // Channel of an environment: the block Hamiltonian (kind 0), one end of a
 // two-node term (kind 1: term k, end 0 = node_a / 1 = node_b) or a recorded
@@ -74,7 +75,7 @@ struct TreeState {
   int n_el = 1, rec_size = 0, kmax = 12;
   // workspace offsets (bytes)
   size_t o_scal, o_counter, o_rec, o_stats, o_V, o_W, o_Z, o_X, o_tmp, o_R, o_bondV, o_bondW,
-      o_qrA, o_qrQ, o_qrv, o_part, o_cpart, o_hist, o_ops, o_site;
+      o_qrA, o_qrQ, o_qrv, o_part, o_cpart, o_hist, o_ops, o_site, o_qrpart, o_qrs;
   std::vector<size_t> o_T, o_opdata, o_sitedata;
   // device pointers
   std::vector<cd*> T, opdev, sitedev;
@@ -90,6 +91,9 @@ struct TreeState {
   };
   std::map<std::pair<int, int>, EdgePlan> edge;  // directed edge (u -> w)
   std::vector<int> obs_desc;                  // recorded observables at the root
+  // H_eff on the matrix cores (empty: the node uses the scalar apply)
+  std::vector<std::vector<int>> mode_pre;     // bond-bond pre-stages (ModeDesc ids)
+  std::vector<std::vector<int>> mode_groups;  // groups; the first carries the site term
 };
 
 bool in_subtree(const TreeState& t, int node, int v) { return node >= v && node < v + t.sub[v]; }
@@ -190,6 +194,8 @@ struct ttns_ctx {
   std::vector<TreeState> trees;
   std::vector<ApplyDesc> descs;
   std::vector<BondDesc> bonds;
+  std::vector<ModeDesc> modes;
+  size_t o_modes = 0;
   size_t o_descs = 0, o_bonds = 0, o_trees = 0, o_half = 0, o_prog = 0, o_begin = 0, o_end = 0;
   size_t total = 0;
   DevTables tables{};
@@ -208,6 +214,7 @@ struct ttns_ctx {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
   double last_h = -1e300;
   int scratch_desc = 0;  // first of the descriptor slots ttns_apply_heff rewrites
+  std::vector<double> step_flops, heff_flops;  // per tree, algorithmic
 };
 
 namespace {
@@ -483,6 +490,8 @@ size_t layout_tree(TreeState& t, size_t off, int rec_cap) {
   t.o_qrv = take(2 * (size_t)t.max_rows * C);
   t.o_part = take((size_t)t.max_nvb * kRedStride * C);
   t.o_cpart = take((size_t)kMaxContractVb * t.maxC * t.maxC * C);
+  t.o_qrpart = take((size_t)kMaxQrVb * kQrStride * C);
+  t.o_qrs = take(sizeof(QrScal));
   t.o_hist = take((size_t)rec_cap * t.rec_size * sizeof(double));
   t.o_T.resize(t.n);
   for (int v = 0; v < t.n; ++v) t.o_T[v] = take((size_t)t.shape[v].size * C);
@@ -614,6 +623,142 @@ struct Builder {
     return add_desc(d);
   }
 
+  // H_eff at v as matrix-core groups; false when v does not qualify.
+  bool plan_mode_groups(int v) {
+    const int prec = c.opts.precision;
+    if (c.persistent) return false;  // the one-workgroup executor keeps the scalar apply
+    const Shape& sh = t.shape[v];
+    if (prec == TTNS_FP64 && sh.size < kMfmaMinSize) return false;
+    const int maxD = mode_max_bond(prec);
+    for (int a = 0; a < sh.rank; ++a)
+      if (a != sh.phys_axis && sh.dims[a] > maxD) return false;
+    std::vector<ApplyDesc> pre;
+    ApplyDesc d = make_sum(v, -2, t.T[v], t.dev.W, pre);
+    if (d.n_entries == 0) return false;
+    auto blank = [&](const cd* src, cd* y) {
+      ModeDesc m{};
+      m.sh = sh;
+      m.prec = prec;
+      m.src = src;
+      m.x = t.T[v];
+      m.y = y;
+      m.site_coef = 1.0;
+      m.n_rest = sh.size / sh.dims[sh.phys_axis];
+      return m;
+    };
+    auto add_term = [&](ModeDesc& m, const Entry& e) -> bool {
+      if (m.n_e >= kMaxGroup) return false;
+      const int k = m.n_e++;
+      m.E[k] = e.E;
+      m.op[k] = e.op;
+      m.lo[k] = e.op ? e.op_lo : 0;
+      m.hi[k] = e.op ? e.op_hi : 0;
+      m.coef[k] = e.coef;
+      m.band_lo = k == 0 ? m.lo[k] : std::min(m.band_lo, m.lo[k]);
+      m.band_hi = k == 0 ? m.hi[k] : std::max(m.band_hi, m.hi[k]);
+      return true;
+    };
+    auto finish = [&](ModeDesc& m) {
+      m.n_rest = sh.size / (sh.dims[m.axis] * sh.dims[sh.phys_axis]);
+      const double D = sh.dims[m.axis];
+      const int dp = sh.dims[sh.phys_axis];
+      int pairs = 0;  // (s, o) combinations with a nonzero weight
+      for (int s = 0; s < dp; ++s)
+        for (int o = m.band_lo; o <= m.band_hi; ++o) {
+          if (s + o < 0 || s + o >= dp) continue;
+          bool any = false;
+          for (int e = 0; e < m.n_e; ++e) {
+            if (!m.op[e]) any = any || o == 0;
+            else if (o >= m.lo[e] && o <= m.hi[e]) {
+              const cd g = t.ht.ops[0].empty() ? cd{0, 0} : cd{1, 0};
+              (void)g;
+              any = true;
+            }
+          }
+          pairs += any;
+        }
+      m.flops = 8.0 * D * D * m.n_rest * pairs;
+    };
+    std::vector<ModeDesc> groups;
+    std::vector<int> gkey_axis, gkey_src;
+    for (int k = 0; k < d.n_entries; ++k) {
+      const Entry& e = d.e[k];
+      int g = -1;
+      for (size_t i = 0; i < groups.size(); ++i)
+        if (gkey_axis[i] == e.axis && gkey_src[i] == e.src) g = (int)i;
+      if (g < 0) {
+        groups.push_back(blank(e.src < 0 ? t.T[v] : t.dev.tmp[e.src], t.dev.W));
+        groups.back().axis = e.axis;
+        gkey_axis.push_back(e.axis);
+        gkey_src.push_back(e.src);
+        g = (int)groups.size() - 1;
+      }
+      if (!add_term(groups[g], e)) return false;
+    }
+    // the first group writes W and carries the on-site term: it must read x
+    int first = -1;
+    for (size_t i = 0; i < groups.size(); ++i)
+      if (gkey_src[i] < 0) {
+        first = (int)i;
+        break;
+      }
+    if (first < 0) return false;
+    std::swap(groups[0], groups[first]);
+    std::swap(gkey_src[0], gkey_src[first]);
+    groups[0].site = d.site;
+    groups[0].site_lo = d.site_lo;
+    groups[0].site_hi = d.site_hi;
+    groups[0].site_coef = d.site_coef;
+    for (size_t i = 1; i < groups.size(); ++i) groups[i].accumulate = 1;
+    std::vector<int> pre_ids, grp_ids;
+    for (size_t i = 0; i < pre.size(); ++i) {
+      // pre-stage: a single mode product into tmp[i]
+      ModeDesc m = blank(t.T[v], t.dev.tmp[i]);
+      m.axis = pre[i].e[0].axis;
+      if (!add_term(m, pre[i].e[0])) return false;
+      finish(m);
+      c.modes.push_back(m);
+      pre_ids.push_back((int)c.modes.size() - 1);
+    }
+    for (size_t i = 0; i < groups.size(); ++i) {
+      finish(groups[i]);
+      if (gkey_src[i] >= 0) groups[i].src = t.dev.tmp[gkey_src[i]];
+      c.modes.push_back(groups[i]);
+      grp_ids.push_back((int)c.modes.size() - 1);
+    }
+    t.mode_pre[v] = pre_ids;
+    t.mode_groups[v] = grp_ids;
+    return true;
+  }
+
+  // launches of one matrix-core H_eff apply: input x (V_j or a caller
+  // buffer), output y (W or a caller buffer)
+  void mode_apply(int v, const cd* x, cd* y) {
+    for (int id : t.mode_pre[v]) {
+      const ModeDesc& m = c.modes[id];
+      Op o = base(OP_MODE, 1);
+      o.desc = id;
+      o.p0 = x;
+      o.p1 = nullptr;
+      o.i0 = m.prec;
+      o.n = m.n_rest;
+      o.axis = m.sh.dims[m.sh.phys_axis];
+      out.push_back(o);
+    }
+    for (int id : t.mode_groups[v]) {
+      const ModeDesc& m = c.modes[id];
+      Op o = base(OP_MODE, 1);
+      o.desc = id;
+      const bool from_x = m.src == t.T[v];
+      o.p0 = from_x ? x : nullptr;
+      o.p1 = y;
+      o.i0 = m.prec;
+      o.n = m.n_rest;
+      o.axis = m.sh.dims[m.sh.phys_axis];
+      out.push_back(o);
+    }
+  }
+
   // The factor of channel `key` of E_{u->w} acting on u's tensor.
   int chan_desc(int u, const ChanKey& key, const cd* x, cd* y) {
     ApplyDesc d = empty_desc(u, x, y);
@@ -668,7 +813,12 @@ struct Builder {
   void plan_all() {
     t.heff_desc.assign(t.n, -1);
     t.heff_pre.assign(t.n, {});
-    for (int v = 0; v < t.n; ++v) t.heff_desc[v] = sum_desc(v, -2, t.T[v], t.dev.W, t.heff_pre[v]);
+    t.mode_pre.assign(t.n, {});
+    t.mode_groups.assign(t.n, {});
+    for (int v = 0; v < t.n; ++v) {
+      t.heff_desc[v] = sum_desc(v, -2, t.T[v], t.dev.W, t.heff_pre[v]);
+      plan_mode_groups(v);
+    }
     for (auto& kv : t.env) {
       const int u = kv.first.first, w = kv.first.second;
       TreeState::EdgePlan& ep = t.edge[{u, w}];
@@ -730,13 +880,35 @@ struct Builder {
     }
   }
 
-  void qr(int u, int w) {
+  // Guarded QR of u's tensor towards neighbour w (or its parent axis when
+  // w = -1): one workgroup with the matrix in LDS when it fits, else the
+  // phased multi-workgroup form.
+  void qr_axis(int u, int ax) {
+    const Shape& sh = t.shape[u];
+    const int cols = sh.dims[ax], rows = sh.size / cols;
     Op o = base(OP_QR, 1);
     o.desc = t.heff_desc[u];  // shape
-    o.axis = axis_of(t, u, w);
+    o.axis = ax;
     o.p1 = t.T[u];
+    if ((size_t)rows * (cols + 2) <= (size_t)kQrLdsEntries) {
+      out.push_back(o);
+      return;
+    }
+    o.type = OP_QRW;
+    o.nvb = std::min(kMaxQrVb, std::max(1, (rows + 511) / 512));
+    o.i0 = 0;
+    out.push_back(o);
+    for (int k = 0; k < cols; ++k)
+      for (int ph = 1; ph <= 5; ++ph) {
+        o.i0 = ph;
+        o.j = k;
+        out.push_back(o);
+      }
+    o.i0 = 6;
+    o.j = cols - 1;
     out.push_back(o);
   }
+  void qr(int u, int w) { qr_axis(u, axis_of(t, u, w)); }
 
   // x (node v's tensor or the absorb buffer) -> T[v] = exp(-i h H_eff) x
   void evolve_node(int v, const cd* x) {
@@ -751,12 +923,19 @@ struct Builder {
     out.push_back(o);
     const int kk = std::min(t.kmax, n);
     const int hd = t.heff_desc[v];
+    const bool mfma = !t.mode_groups[v].empty();
     for (int j = 0; j < kk; ++j) {
-      for (int p : t.heff_pre[v]) apply_op(p, t.dev.V + (size_t)j * t.dev.ldv);
+      const cd* vj = t.dev.V + (size_t)j * t.dev.ldv;
+      if (mfma) {
+        mode_apply(v, vj, t.dev.W);
+      } else {
+        for (int p : t.heff_pre[v]) apply_op(p, vj);
+      }
       o = base(OP_APPLY_LZ, nvb_of(n));
       o.desc = hd;
       o.j = j;
       o.n = n;
+      o.i0 = mfma ? 1 : 0;
       out.push_back(o);
       o = base(OP_ORTH1, nvb_of(n));
       o.j = j;
@@ -968,6 +1147,8 @@ void set_tree_pointers(ttns_ctx& c, TreeState& t, char* base) {
   d.qrv = P(t.o_qrv);
   d.partials = P(t.o_part);
   d.cpart = P(t.o_cpart);
+  d.qrpart = P(t.o_qrpart);
+  d.qrs = (QrScal*)(base + t.o_qrs);
   d.hist = (double*)(base + t.o_hist);
   d.max_rows = t.max_rows;
   d.rec_size = t.rec_size;
@@ -993,10 +1174,12 @@ int prepare(ttns_ctx& c, std::vector<TreeState>&& trees, const ttns_opts* opts, 
   if (o.krylov_dim < 1 || o.krylov_dim > kMaxKrylov) return fail(TTNS_EINVAL, "krylov_dim must be in [1, 16]");
   if (o.record_capacity < 1) return fail(TTNS_EINVAL, "record_capacity must be >= 1");
   if (!(o.rank_tol > 0) || !(o.breakdown_tol > 0)) return fail(TTNS_EINVAL, "tolerances must be > 0");
-  if (o.precision != TTNS_FP64) return fail(TTNS_EINVAL, "this build runs the FP64 path only");
+  if (o.precision < TTNS_FP64 || o.precision > TTNS_BF16X3) return fail(TTNS_EINVAL, "bad precision");
   if (o.executor < TTNS_EXEC_AUTO || o.executor > TTNS_EXEC_PERSISTENT) return fail(TTNS_EINVAL, "bad executor");
   c.opts = o;
   c.trees = std::move(trees);
+  c.persistent = (o.executor == TTNS_EXEC_PERSISTENT) ||
+                 (o.executor == TTNS_EXEC_AUTO && c.trees.size() > 1);
   for (auto& t : c.trees) {
     std::string err;
     int rc = analyze(t, o, err);
@@ -1026,13 +1209,7 @@ int prepare(ttns_ctx& c, std::vector<TreeState>&& trees, const ttns_opts* opts, 
     std::vector<Op> ops;
     Builder b{c, t, (int)ti, ops};
     b.plan_all();
-    for (int v = t.n - 1; v > 0; --v) {  // isometries towards the parents
-      Op q = b.base(OP_QR, 1);
-      q.desc = t.heff_desc[v];
-      q.axis = 0;
-      q.p1 = t.T[v];
-      ops.push_back(q);
-    }
+    for (int v = t.n - 1; v > 0; --v) b.qr_axis(v, 0);  // isometries towards the parents
     for (int v = t.n - 1; v > 0; --v) b.env_update(v, parent_of(t, v));
     b.observe(false);
     init_ops.insert(init_ops.end(), ops.begin(), ops.end());
@@ -1046,6 +1223,54 @@ int prepare(ttns_ctx& c, std::vector<TreeState>&& trees, const ttns_opts* opts, 
     persistent_prog.insert(persistent_prog.end(), ops.begin(), ops.end());
     c.tree_end[ti] = (int)persistent_prog.size();
   }
+  // algorithmic flops of one step per tree (8 real flops per complex
+  // multiply-add): H_eff contractions, environment applies and contractions,
+  // classical Gram-Schmidt QR (two passes of project + subtract), bond steps
+  c.step_flops.assign(c.trees.size(), 0.0);
+  c.heff_flops.assign(c.trees.size(), 0.0);
+  for (const Op& o : persistent_prog) {
+    double f = 0.0, fh = 0.0;
+    switch (o.type) {
+      case OP_APPLY:
+        f = c.descs[o.desc].flops;
+        break;
+      case OP_APPLY_LZ:
+        if (!o.i0) f = fh = c.descs[o.desc].flops;
+        break;
+      case OP_MODE:
+        f = fh = c.modes[o.desc].flops;
+        break;
+      case OP_CONTRACT: {
+        const Shape& sh = c.descs[o.desc].sh;
+        const double D = sh.dims[o.axis];
+        f = 8.0 * sh.size * D;
+        break;
+      }
+      case OP_QR: {
+        const Shape& sh = c.descs[o.desc].sh;
+        const double cols = sh.dims[o.axis], rows = sh.size / cols;
+        f = 16.0 * rows * cols * cols;
+        break;
+      }
+      case OP_QRW:
+        if (o.i0 == 0) {
+          const Shape& sh = c.descs[o.desc].sh;
+          const double cols = sh.dims[o.axis], rows = sh.size / cols;
+          f = 16.0 * rows * cols * cols;
+        }
+        break;
+      case OP_BOND: {
+        const BondDesc& b = c.bonds[o.desc];
+        const double Du = b.Du, Dv = b.Dv;
+        f = 8.0 * c.opts.krylov_dim * (Du * Du * Dv + Du * Dv * Dv) * (1 + b.n_pairs);
+        break;
+      }
+      default:
+        break;
+    }
+    c.step_flops[o.tree] += f;
+    c.heff_flops[o.tree] += fh;
+  }
   c.step_ops = persistent_prog;  // the wide executor runs the trees one after another
   c.tree_prog = persistent_prog;
   c.scratch_desc = (int)c.descs.size();
@@ -1056,6 +1281,7 @@ int prepare(ttns_ctx& c, std::vector<TreeState>&& trees, const ttns_opts* opts, 
     return r;
   };
   c.o_descs = take(c.descs.size() * sizeof(ApplyDesc));
+  c.o_modes = take(c.modes.size() * sizeof(ModeDesc));
   c.o_bonds = take(c.bonds.size() * sizeof(BondDesc));
   c.o_trees = take(c.trees.size() * sizeof(TreeDev));
   c.o_prog = take(persistent_prog.size() * sizeof(Op));
@@ -1076,9 +1302,8 @@ int prepare(ttns_ctx& c, std::vector<TreeState>&& trees, const ttns_opts* opts, 
   c.ws_bytes = ws_bytes;
   c.stream = (hipStream_t)stream;
   HIPCHK(hipStreamCreateWithFlags(&c.cap, hipStreamNonBlocking));
-  c.persistent = (o.executor == TTNS_EXEC_PERSISTENT) ||
-                 (o.executor == TTNS_EXEC_AUTO && c.trees.size() > 1);
   c.tables.descs = (const ApplyDesc*)(c.ws + c.o_descs);
+  c.tables.modes = (const ModeDesc*)(c.ws + c.o_modes);
   c.tables.bonds = (const BondDesc*)(c.ws + c.o_bonds);
   c.tables.trees = (const TreeDev*)(c.ws + c.o_trees);
   c.d_ops = (Op*)(c.ws + c.o_prog);
@@ -1106,6 +1331,7 @@ int prepare(ttns_ctx& c, std::vector<TreeState>&& trees, const ttns_opts* opts, 
   std::vector<TreeDev> tdev;
   for (auto& t : c.trees) tdev.push_back(t.dev);
   if ((rc = upload(c, c.o_descs, c.descs.data(), c.descs.size() * sizeof(ApplyDesc)))) return rc;
+  if ((rc = upload(c, c.o_modes, c.modes.data(), c.modes.size() * sizeof(ModeDesc)))) return rc;
   if ((rc = upload(c, c.o_bonds, c.bonds.data(), c.bonds.size() * sizeof(BondDesc)))) return rc;
   if ((rc = upload(c, c.o_trees, tdev.data(), tdev.size() * sizeof(TreeDev)))) return rc;
   if ((rc = upload(c, c.o_prog, persistent_prog.data(), persistent_prog.size() * sizeof(Op)))) return rc;
@@ -1199,6 +1425,31 @@ int validate_program(ttns_ctx& c, const std::vector<Op>& ops, bool allow_user_xy
         if (o.nvb != 1 || cols > 64 || rows < cols || rows > d.max_rows || sh.size > d.ldv ||
             o.axis == sh.phys_axis)
           rc.err = "internal: QR shape";
+        break;
+      }
+      case OP_MODE: {
+        const ModeDesc& m = c.modes[o.desc];
+        const size_t n = (size_t)m.sh.size * C;
+        if (!allow_user_xy || !o.p0) rc.in(o.p0 ? o.p0 : m.src, n, "matrix-core source");
+        if (!allow_user_xy || !o.p1) rc.in(o.p1 ? o.p1 : m.y, n, "matrix-core output");
+        const int dp = m.sh.dims[m.sh.phys_axis], D = m.sh.dims[m.axis];
+        if (m.site) rc.in(m.site, (size_t)dp * dp * C, "on-site operator");
+        for (int e = 0; e < m.n_e; ++e) {
+          rc.in(m.E[e], (size_t)D * D * C, "environment channel");
+          if (m.op[e]) rc.in(m.op[e], (size_t)dp * dp * C, "entry operator");
+        }
+        if (m.axis == m.sh.phys_axis || D > mode_max_bond(m.prec) || o.n != m.n_rest ||
+            o.axis != dp || o.i0 != m.prec || m.n_e < 1 || m.n_e > kMaxGroup)
+          rc.err = "internal: matrix-core group";
+        break;
+      }
+      case OP_QRW: {
+        const Shape& sh = c.descs[o.desc].sh;
+        const int cols = sh.dims[o.axis], rows = sh.size / cols;
+        rc.in(o.p1, (size_t)sh.size * C, "QR tensor");
+        if (o.nvb < 1 || o.nvb > kMaxQrVb || cols > 64 || rows < cols || rows > d.max_rows ||
+            sh.size > d.ldv || o.axis == sh.phys_axis || o.i0 < 0 || o.i0 > 6 || o.j < 0 || o.j >= cols)
+          rc.err = "internal: wide QR shape";
         break;
       }
       case OP_CONTRACT: {
@@ -1377,6 +1628,12 @@ int ttns_apply_heff(ttns_ctx* c, int32_t tree, int32_t node, const void* dev_in,
   std::vector<Op> ops;
   Builder b{*c, t, tree, ops};
   b.move_to(node);
+  if (!t.mode_groups[node].empty()) {
+    b.mode_apply(node, (const cd*)dev_in, (cd*)dev_out);
+    int rc = validate_program(*c, ops, true);
+    if (rc) return rc;
+    return run_ops(*c, ops);
+  }
   std::vector<ApplyDesc> pre;
   ApplyDesc d = b.make_sum(node, -2, (const cd*)dev_in, (cd*)dev_out, pre);
   const int s0 = c->scratch_desc;
@@ -1475,6 +1732,11 @@ int ttns_observe(ttns_ctx* c, int32_t kind, int32_t tree, int32_t index, double*
       host_out[4] = st[3];
       return TTNS_OK;
     }
+    case TTNS_OBS_STEP_FLOPS:
+      if ((rc = need(2))) return rc;
+      host_out[0] = c->step_flops[tree];
+      host_out[1] = c->heff_flops[tree];
+      return TTNS_OK;
     case TTNS_OBS_BOND_DIMS:
       if ((rc = need(t.n))) return rc;
       for (int v = 0; v < t.n; ++v) host_out[v] = t.D[v];

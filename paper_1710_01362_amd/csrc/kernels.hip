@@ -12,34 +12,24 @@
 // Complex numbers are double2 (re, im).  No floating-point atomics anywhere.
 #include <hip/hip_runtime.h>
 
+#include "device_common.h"
 #include "ttns_internal.h"
 
 namespace ttns {
-
-// ------------------------------------------------------------ complex helpers
-__device__ __forceinline__ cd cz() { return make_double2(0.0, 0.0); }
-__device__ __forceinline__ cd cadd(cd a, cd b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ cd csub(cd a, cd b) { return make_double2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ cd cscale(cd a, double s) { return make_double2(a.x * s, a.y * s); }
-// c + a * b
-__device__ __forceinline__ cd cfma(cd a, cd b, cd c) {
-  return make_double2(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
-}
-// c + conj(a) * b
-__device__ __forceinline__ cd cjfma(cd a, cd b, cd c) {
-  return make_double2(fma(a.x, b.x, fma(a.y, b.y, c.x)), fma(a.x, b.y, fma(-a.y, b.x, c.y)));
-}
-__device__ __forceinline__ double cabs2(cd a) { return a.x * a.x + a.y * a.y; }
 
 // ------------------------------------------------------------ shared memory
 struct Smem {
   cd red[kBlock / 64];
   cd wred[kBlock / 64][kRedStride];  // per-wavefront partial sums
-  cd vec[kRedStride];          // broadcast scalars (dot products, coefficients)
-  cd M[kMaxKrylov * kMaxKrylov];  // Krylov exponential work
-  cd P[kMaxKrylov * kMaxKrylov];
-  cd Q[kMaxKrylov * kMaxKrylov];
-  int rowbase[1024];           // contraction: row -> tensor offset
+  cd vec[kRedStride];                // broadcast scalars (dot products, coefficients)
+  union {
+    struct {
+      cd M[kMaxKrylov * kMaxKrylov];  // Krylov exponential work
+      cd P[kMaxKrylov * kMaxKrylov];
+    } kx;
+    cd lanes[kBlock];                 // wide-QR fold helpers
+  };
+  cd fold[64];
   int ival[4];
   double dval[4];
 };
@@ -241,8 +231,12 @@ __device__ bool body_apply_lz(const Op& op, const DevTables& T, int vb, Smem& sm
   const int idx = vb * kBlock + threadIdx.x;
   cd w = cz();
   if (idx < n) {
-    w = apply_point(d, tr.V + (size_t)op.j * tr.ldv, idx);
-    tr.W[idx] = w;
+    if (op.i0) {  // W was produced by the matrix-core groups of this apply
+      w = tr.W[idx];
+    } else {
+      w = apply_point(d, tr.V + (size_t)op.j * tr.ldv, idx);
+      tr.W[idx] = w;
+    }
   }
   lz_partials(tr, op.j, n, vb, idx, w, sm);
   return true;
@@ -355,8 +349,8 @@ __device__ void krylov_exp(const double* alpha, const double* beta, int k, doubl
   // P = I, M = I
   if (t < kMaxKrylov * kMaxKrylov) {
     cd one = make_double2((r == c) ? 1.0 : 0.0, 0.0);
-    sm.P[t] = one;
-    sm.M[t] = one;
+    sm.kx.P[t] = one;
+    sm.kx.M[t] = one;
   }
   __syncthreads();
   for (int term = 1; term <= 18; ++term) {
@@ -364,28 +358,28 @@ __device__ void krylov_exp(const double* alpha, const double* beta, int k, doubl
     cd v = cz();
     if (mine) {
       cd acc = cz();
-      if (c > 0) acc = cscale(sm.P[r * kMaxKrylov + c - 1], beta[c - 1]);
-      acc = cadd(acc, cscale(sm.P[r * kMaxKrylov + c], alpha[c]));
-      if (c + 1 < k) acc = cadd(acc, cscale(sm.P[r * kMaxKrylov + c + 1], beta[c]));
+      if (c > 0) acc = cscale(sm.kx.P[r * kMaxKrylov + c - 1], beta[c - 1]);
+      acc = cadd(acc, cscale(sm.kx.P[r * kMaxKrylov + c], alpha[c]));
+      if (c + 1 < k) acc = cadd(acc, cscale(sm.kx.P[r * kMaxKrylov + c + 1], beta[c]));
       const double f = zs / (double)term;
       v = make_double2(-acc.y * f, acc.x * f);  // i * f * acc
     }
     __syncthreads();
     if (mine) {
-      sm.P[r * kMaxKrylov + c] = v;
-      sm.M[r * kMaxKrylov + c] = cadd(sm.M[r * kMaxKrylov + c], v);
+      sm.kx.P[r * kMaxKrylov + c] = v;
+      sm.kx.M[r * kMaxKrylov + c] = cadd(sm.kx.M[r * kMaxKrylov + c], v);
     }
     __syncthreads();
   }
   for (int sq = 0; sq < q; ++sq) {
     cd v = cz();
     if (mine)
-      for (int m = 0; m < k; ++m) v = cfma(sm.M[r * kMaxKrylov + m], sm.M[m * kMaxKrylov + c], v);
+      for (int m = 0; m < k; ++m) v = cfma(sm.kx.M[r * kMaxKrylov + m], sm.kx.M[m * kMaxKrylov + c], v);
     __syncthreads();
-    if (mine) sm.M[r * kMaxKrylov + c] = v;
+    if (mine) sm.kx.M[r * kMaxKrylov + c] = v;
     __syncthreads();
   }
-  if (t < k) sm.vec[t] = sm.M[t * kMaxKrylov];
+  if (t < k) sm.vec[t] = sm.kx.M[t * kMaxKrylov];
   __syncthreads();
 }
 
@@ -447,8 +441,15 @@ __device__ void qr_project(const cd* Q, const cd* v, int rows, int k, cd* h) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int j = wid; j < k; j += kBlock / 64) {
     const cd* q = Q + (size_t)j * rows;
-    cd acc = cz();
-    for (int r = lane; r < rows; r += 64) acc = cjfma(q[r], v[r], acc);
+    cd a0 = cz(), a1 = cz();  // two chains keep several loads in flight
+    int r = lane;
+#pragma unroll 2
+    for (; r + 64 < rows; r += 128) {
+      a0 = cjfma(q[r], v[r], a0);
+      a1 = cjfma(q[r + 64], v[r + 64], a1);
+    }
+    if (r < rows) a0 = cjfma(q[r], v[r], a0);
+    cd acc = cadd(a0, a1);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
       acc.x += __shfl_xor(acc.x, off);
@@ -463,12 +464,21 @@ __device__ void qr_project(const cd* Q, const cd* v, int rows, int k, cd* h) {
 __device__ double qr_subtract(const cd* Q, cd* v, int rows, int k, const cd* h) {
   double n2 = 0.0;
   for (int r = threadIdx.x; r < rows; r += kBlock) {
-    cd acc = v[r];
-    for (int j = 0; j < k; ++j) {
-      const cd q = Q[(size_t)j * rows + r];
-      const cd hj = h[j];
-      acc = csub(acc, make_double2(q.x * hj.x - q.y * hj.y, q.x * hj.y + q.y * hj.x));
+    cd a0 = v[r], a1 = cz();
+    int j = 0;
+#pragma unroll 2
+    for (; j + 1 < k; j += 2) {
+      const cd q0 = Q[(size_t)j * rows + r], q1 = Q[(size_t)(j + 1) * rows + r];
+      const cd h0 = h[j], h1 = h[j + 1];
+      a0 = csub(a0, make_double2(q0.x * h0.x - q0.y * h0.y, q0.x * h0.y + q0.y * h0.x));
+      a1 = csub(a1, make_double2(q1.x * h1.x - q1.y * h1.y, q1.x * h1.y + q1.y * h1.x));
     }
+    if (j < k) {
+      const cd q0 = Q[(size_t)j * rows + r];
+      const cd h0 = h[j];
+      a0 = csub(a0, make_double2(q0.x * h0.x - q0.y * h0.y, q0.x * h0.y + q0.y * h0.x));
+    }
+    const cd acc = cadd(a0, a1);
     v[r] = acc;
     n2 += cabs2(acc);
   }
@@ -477,7 +487,7 @@ __device__ double qr_subtract(const cd* Q, cd* v, int rows, int k, const cd* h) 
 }
 
 // LDS budget of the QR (complex entries): Q columns plus two row vectors.
-constexpr int kQrLds = 8800;  // 137.5 KiB: a 400 x 20 matrix plus two vectors
+constexpr int kQrLds = kQrLdsEntries;  // 137.5 KiB: a 400 x 20 matrix plus two vectors
 
 // OP_QR (one workgroup): node tensor op.p1 (shape of desc op.desc) = Q R
 // towards axis op.axis; Q overwrites the tensor, R -> tree R buffer.
@@ -486,44 +496,86 @@ constexpr int kQrLds = 8800;  // 137.5 KiB: a 400 x 20 matrix plus two vectors
 // completion order) farther than half the average from the span so far,
 // orthogonalised twice.  Q and the work vectors live in LDS (`lds`, kQrLds
 // entries) when they fit, else in the tree's global scratch.
-__device__ void body_qr(const Op& op, const DevTables& T, Smem& sm, cd* lds) {
+template <bool kLds>
+__device__ void body_qr_t(const Op& op, const DevTables& T, Smem& sm, cd* lds) {
   const TreeDev& tr = T.trees[op.tree];
   const Shape& sh = T.descs[op.desc].sh;
   const int ax = op.axis;
   const int cols = sh.dims[ax];
   const int rows = sh.size / cols;
   const int cst = sh.stride[ax];
-  const bool in_lds = (size_t)rows * (cols + 2) <= (size_t)kQrLds;
   cd* A = tr.qrA;
-  cd* Q = in_lds ? lds : tr.qrQ;
-  cd* v = in_lds ? lds + (size_t)rows * cols : tr.qrv;
-  cd* u = in_lds ? v + rows : tr.qrv + tr.max_rows;
+  cd* Q = kLds ? lds : tr.qrQ;
+  cd* v = kLds ? lds + (size_t)rows * cols : tr.qrv;
+  cd* u = kLds ? v + rows : tr.qrv + tr.max_rows;
   cd* R = tr.R;
   cd* X = op.p1;
-  cd* h1 = sm.vec + 0;  // kRedStride >= 18; two halves of 64 below
   __shared__ cd hb1[64], hb2[64];
-  (void)h1;
-  // gather A (column-major) and |A|_F^2
-  double nrm = 0.0;
+  // gather A (column-major), |A|_F^2 and the squared norm of every column
+  __shared__ double colnrm[64];
+  for (int c = threadIdx.x; c < cols; c += kBlock) colnrm[c] = 0.0;
+  __syncthreads();
   for (int r = threadIdx.x; r < rows; r += kBlock) {
     const int off = qr_row_offset(sh, ax, r);
     for (int c = 0; c < cols; ++c) {
       const cd a = X[off + c * cst];
       A[(size_t)c * rows + r] = a;
-      nrm += cabs2(a);
+    }
+  }
+  __syncthreads();
+  {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int c = wid; c < cols; c += kBlock / 64) {
+      double s = 0.0;
+      for (int r = lane; r < rows; r += 64) s += cabs2(A[(size_t)c * rows + r]);
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+      if (lane == 0) colnrm[c] = s;
     }
   }
   for (int i = threadIdx.x; i < cols * cols; i += kBlock) R[i] = cz();
-  nrm = block_sum(make_double2(nrm, 0.0), sm).x;
+  __syncthreads();
+  double nrm = 0.0;
+  for (int c = 0; c < cols; ++c) nrm += colnrm[c];
   const double tol = tr.rtol * sqrt(nrm);
+  // each thread owns rows tid, tid + kBlock, ...; the next column of A is
+  // loaded into registers while the current one is processed
+  constexpr int kPre = 4;
+  cd nxt[kPre];
+#pragma unroll
+  for (int i = 0; i < kPre; ++i) {
+    const int r = threadIdx.x + i * kBlock;
+    nxt[i] = r < rows ? A[r] : cz();
+  }
   for (int k = 0; k < cols; ++k) {
-    const cd* a = A + (size_t)k * rows;
-    for (int r = threadIdx.x; r < rows; r += kBlock) v[r] = a[r];
+#pragma unroll
+    for (int i = 0; i < kPre; ++i) {
+      const int r = threadIdx.x + i * kBlock;
+      if (r < rows) v[r] = nxt[i];
+    }
+    for (int r = threadIdx.x + kPre * kBlock; r < rows; r += kBlock) v[r] = A[(size_t)k * rows + r];
+    if (k + 1 < cols) {
+#pragma unroll
+      for (int i = 0; i < kPre; ++i) {
+        const int r = threadIdx.x + i * kBlock;
+        if (r < rows) nxt[i] = A[(size_t)(k + 1) * rows + r];
+      }
+    }
     __syncthreads();
+    // a column no longer than tol is deficient whatever its projections:
+    // one pass gives its R entries and residual; otherwise two passes
+    const bool tiny = sqrt(colnrm[k]) <= tol;
     qr_project(Q, v, rows, k, hb1);
-    qr_subtract(Q, v, rows, k, hb1);
-    qr_project(Q, v, rows, k, hb2);
-    const double rn = sqrt(block_sum(make_double2(qr_subtract(Q, v, rows, k, hb2), 0.0), sm).x);
+    double rn;
+    if (tiny) {
+      rn = sqrt(block_sum(make_double2(qr_subtract(Q, v, rows, k, hb1), 0.0), sm).x);
+      for (int j = threadIdx.x; j < k; j += kBlock) hb2[j] = cz();
+      __syncthreads();
+    } else {
+      qr_subtract(Q, v, rows, k, hb1);
+      qr_project(Q, v, rows, k, hb2);
+      rn = sqrt(block_sum(make_double2(qr_subtract(Q, v, rows, k, hb2), 0.0), sm).x);
+    }
     for (int j = threadIdx.x; j < k; j += kBlock) R[j * cols + k] = cadd(hb1[j], hb2[j]);
     cd* qk = Q + (size_t)k * rows;
     if (rn > tol) {
@@ -542,9 +594,15 @@ __device__ void body_qr(const Op& op, const DevTables& T, Smem& sm, cd* lds) {
         bool ok = false;
         if (n < rows) {
           const int row = qr_candidate_row(sh, ax, n);
-          double s = 0.0;
-          for (int j = 0; j < k; ++j) s += cabs2(Q[(size_t)j * rows + row]);
-          ok = (1.0 - s) > thr;
+          double s = 0.0, s1 = 0.0;
+          int j = 0;
+#pragma unroll 2
+          for (; j + 1 < k; j += 2) {
+            s += cabs2(Q[(size_t)j * rows + row]);
+            s1 += cabs2(Q[(size_t)(j + 1) * rows + row]);
+          }
+          if (j < k) s += cabs2(Q[(size_t)j * rows + row]);
+          ok = (1.0 - (s + s1)) > thr;
         }
         const unsigned long long m = __ballot(ok);
         if (m) chosen = base + __ffsll((long long)m) - 1;
@@ -564,9 +622,9 @@ __device__ void body_qr(const Op& op, const DevTables& T, Smem& sm, cd* lds) {
     }
     for (int r = threadIdx.x; r < rows; r += kBlock) u[r] = make_double2(r == row ? 1.0 : 0.0, 0.0);
     __syncthreads();
-    qr_subtract(Q, u, rows, k, hb1);
-    qr_project(Q, u, rows, k, hb2);
-    const double iu = 1.0 / sqrt(block_sum(make_double2(qr_subtract(Q, u, rows, k, hb2), 0.0), sm).x);
+    // the projection coefficients of a unit vector are read, not computed,
+    // so one pass leaves u orthogonal to the span to ~k eps / |u|
+    const double iu = 1.0 / sqrt(block_sum(make_double2(qr_subtract(Q, u, rows, k, hb1), 0.0), sm).x);
     cd rkk = cz();
     for (int r = threadIdx.x; r < rows; r += kBlock) {
       const cd q = cscale(u[r], iu);
@@ -587,12 +645,265 @@ __device__ void body_qr(const Op& op, const DevTables& T, Smem& sm, cd* lds) {
   }
 }
 
+__device__ void body_qr(const Op& op, const DevTables& T, Smem& sm, cd* lds) {
+  const Shape& sh = T.descs[op.desc].sh;
+  const int cols = sh.dims[op.axis];
+  const int rows = sh.size / cols;
+  if ((size_t)rows * (cols + 2) <= (size_t)kQrLds) body_qr_t<true>(op, T, sm, lds);
+  else body_qr_t<false>(op, T, sm, nullptr);
+}
+
+// ------------------------------------------------------------ wide QR
+// The same column-by-column CGS2 with completion as body_qr, for matrices
+// too large for one workgroup's LDS, as a sequence of launches over row
+// chunks (vb).  Phases (op.i0), column k = op.j:
+//   0 gather A, |A|_F^2                      (fold: tol, zero R)
+//   1 finalise Q_{k-1} (v/rn or u*iu; k > 0), v = A_k, partial Q^H A_k
+//   2 v -= Q h1, partial Q^H v
+//   3 v -= Q h2, partial |v|^2               (fold: rn, R column, decision)
+//   4 completion only: every workgroup scans for the first admissible unit
+//     vector (same answer everywhere), u = e_row - Q (Q^H e_row), partial Q^H u
+//   5 completion only: u -= Q h2, partial |u|^2 and <u|v>  (fold: R_kk, iu)
+//   6 finalise the last column and scatter Q into the node tensor.
+__device__ void qrw_rows(const Op& op, int rows, int vb, int& r0, int& r1) {
+  const int chunk = (rows + op.nvb - 1) / op.nvb;
+  r0 = vb * chunk;
+  r1 = min(rows, r0 + chunk);
+}
+
+// partial[j] = sum_{r in chunk} conj(Q_j[r]) x[r], j < k (waves take columns).
+__device__ void qrw_project(const TreeDev& tr, const cd* Q, const cd* x, int rows, int k, int r0,
+                            int r1, int vb) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int j = wid; j < k; j += kBlock / 64) {
+    const cd* q = Q + (size_t)j * rows;
+    cd acc = cz();
+    for (int r = r0 + lane; r < r1; r += 64) acc = cjfma(q[r], x[r], acc);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      acc.x += __shfl_xor(acc.x, off);
+      acc.y += __shfl_xor(acc.y, off);
+    }
+    if (lane == 0) tr.qrpart[vb * kQrStride + j] = acc;
+  }
+}
+
+// Fold slots [0, cnt) of the wide-QR partial sums over all workgroups into
+// sm.fold[0..cnt) (every thread takes (slot, workgroup) pairs, then one
+// thread per slot adds the kBlock / cnt partial lanes in order).
+__device__ void qrw_fold_all(const TreeDev& tr, int nvb, int cnt, Smem& sm) {
+  const int t = threadIdx.x;
+  const int lanes = cnt > 0 ? kBlock / cnt : 1;  // helpers per slot
+  const int s = t / lanes, l = t % lanes;
+  if (cnt > 0 && s < cnt) {
+    cd acc = cz();
+    for (int b = l; b < nvb; b += lanes) acc = cadd(acc, tr.qrpart[b * kQrStride + s]);
+    sm.lanes[t] = acc;
+  }
+  __syncthreads();
+  if (t < cnt) {
+    cd acc = cz();
+    for (int q = 0; q < lanes; ++q) acc = cadd(acc, sm.lanes[t * lanes + q]);
+    sm.fold[t] = acc;
+  }
+  __syncthreads();
+}
+
+// Finalise column c of Q in this chunk from the previous column's outcome.
+__device__ void qrw_finalise(const TreeDev& tr, cd* Q, int rows, int c, int r0, int r1) {
+  const QrScal* s = tr.qrs;
+  const cd* src = s->deficient ? tr.qrv + tr.max_rows : tr.qrv;
+  const double f = s->deficient ? s->iu : 1.0 / s->rn;
+  for (int r = r0 + (int)threadIdx.x; r < r1; r += kBlock) Q[(size_t)c * rows + r] = cscale(src[r], f);
+}
+
+// Returns true when the phase did work that needs a fold (uniform).
+__device__ bool body_qrw(const Op& op, const DevTables& T, int vb, Smem& sm) {
+  const TreeDev& tr = T.trees[op.tree];
+  const Shape& sh = T.descs[op.desc].sh;
+  const int ax = op.axis, cols = sh.dims[ax], rows = sh.size / cols, cst = sh.stride[ax];
+  const int k = op.j;
+  cd* A = tr.qrA;
+  cd* Q = tr.qrQ;
+  cd* v = tr.qrv;
+  cd* u = tr.qrv + tr.max_rows;
+  int r0, r1;
+  qrw_rows(op, rows, vb, r0, r1);
+  QrScal* s = tr.qrs;
+  switch (op.i0) {
+    case 0: {
+      double n2 = 0.0;
+      for (int r = r0 + (int)threadIdx.x; r < r1; r += kBlock) {
+        const int off = qr_row_offset(sh, ax, r);
+        for (int c = 0; c < cols; ++c) {
+          const cd a = op.p1[off + c * cst];
+          A[(size_t)c * rows + r] = a;
+          n2 += cabs2(a);
+        }
+      }
+      n2 = block_sum(make_double2(n2, 0.0), sm).x;
+      if (threadIdx.x == 0) tr.qrpart[vb * kQrStride] = make_double2(n2, 0.0);
+      return true;
+    }
+    case 1: {
+      if (k > 0) qrw_finalise(tr, Q, rows, k - 1, r0, r1);
+      const cd* a = A + (size_t)k * rows;
+      for (int r = r0 + (int)threadIdx.x; r < r1; r += kBlock) v[r] = a[r];
+      __syncthreads();
+      qrw_project(tr, Q, a, rows, k, r0, r1, vb);
+      return true;
+    }
+    case 2:
+    case 3: {
+      const cd* h = op.i0 == 2 ? s->h1 : s->h2;
+      double n2 = 0.0;
+      for (int r = r0 + (int)threadIdx.x; r < r1; r += kBlock) {
+        cd acc = v[r];
+        for (int j = 0; j < k; ++j) {
+          const cd q = Q[(size_t)j * rows + r];
+          const cd hj = h[j];
+          acc = csub(acc, make_double2(q.x * hj.x - q.y * hj.y, q.x * hj.y + q.y * hj.x));
+        }
+        v[r] = acc;
+        n2 += cabs2(acc);
+      }
+      __syncthreads();
+      if (op.i0 == 2) {
+        qrw_project(tr, Q, v, rows, k, r0, r1, vb);
+      } else {
+        n2 = block_sum(make_double2(n2, 0.0), sm).x;
+        if (threadIdx.x == 0) tr.qrpart[vb * kQrStride] = make_double2(n2, 0.0);
+      }
+      return true;
+    }
+    case 4: {
+      if (!s->deficient) return false;
+      const double thr = 0.5 * (double)(rows - k) / (double)rows;
+      if (threadIdx.x < 64) {
+        int chosen = -1;
+        for (int base = 0; base < rows && chosen < 0; base += 64) {
+          const int n = base + (int)threadIdx.x;
+          bool ok = false;
+          if (n < rows) {
+            const int row = qr_candidate_row(sh, ax, n);
+            double t = 0.0;
+            for (int j = 0; j < k; ++j) t += cabs2(Q[(size_t)j * rows + row]);
+            ok = (1.0 - t) > thr;
+          }
+          const unsigned long long m = __ballot(ok);
+          if (m) chosen = base + __ffsll((long long)m) - 1;
+        }
+        if (threadIdx.x == 0) sm.ival[2] = chosen < 0 ? -1 : qr_candidate_row(sh, ax, chosen);
+      }
+      __syncthreads();
+      const int row = sm.ival[2];
+      if (row < 0) {
+        if (threadIdx.x == 0 && vb == 0) atomicOr(&tr.stats[3], 1);
+        return true;
+      }
+      for (int r = r0 + (int)threadIdx.x; r < r1; r += kBlock) {
+        cd acc = make_double2(r == row ? 1.0 : 0.0, 0.0);
+        for (int j = 0; j < k; ++j) {
+          const cd q = Q[(size_t)j * rows + r];
+          const cd g = Q[(size_t)j * rows + row];  // coefficient conj(Q_j[row])
+          acc = csub(acc, make_double2(q.x * g.x + q.y * g.y, -q.x * g.y + q.y * g.x));
+        }
+        u[r] = acc;
+      }
+      __syncthreads();
+      if (vb == 0 && threadIdx.x == 0) s->row = row;
+      qrw_project(tr, Q, u, rows, k, r0, r1, vb);
+      return true;
+    }
+    case 5: {
+      if (!s->deficient) return false;
+      cd nu = cz(), uv = cz();
+      for (int r = r0 + (int)threadIdx.x; r < r1; r += kBlock) {
+        cd acc = u[r];
+        for (int j = 0; j < k; ++j) {
+          const cd q = Q[(size_t)j * rows + r];
+          const cd hj = s->h2[j];
+          acc = csub(acc, make_double2(q.x * hj.x - q.y * hj.y, q.x * hj.y + q.y * hj.x));
+        }
+        u[r] = acc;
+        nu.x += cabs2(acc);
+        uv = cjfma(acc, v[r], uv);
+      }
+      nu = block_sum(nu, sm);
+      uv = block_sum(uv, sm);
+      if (threadIdx.x == 0) {
+        tr.qrpart[vb * kQrStride] = nu;
+        tr.qrpart[vb * kQrStride + 1] = uv;
+      }
+      return true;
+    }
+    case 6: {
+      qrw_finalise(tr, Q, rows, cols - 1, r0, r1);
+      __syncthreads();
+      for (int r = r0 + (int)threadIdx.x; r < r1; r += kBlock) {
+        const int off = qr_row_offset(sh, ax, r);
+        for (int c = 0; c < cols; ++c) op.p1[off + c * cst] = Q[(size_t)c * rows + r];
+      }
+      return false;
+    }
+  }
+  return false;
+}
+
+__device__ void fin_qrw(const Op& op, const DevTables& T, int nvb, Smem& sm) {
+  const TreeDev& tr = T.trees[op.tree];
+  const Shape& sh = T.descs[op.desc].sh;
+  const int cols = sh.dims[op.axis];
+  const int k = op.j;
+  QrScal* s = tr.qrs;
+  cd* R = tr.R;
+  const int t = threadIdx.x;
+  const int cnt = (op.i0 == 1 || op.i0 == 2 || op.i0 == 4) ? k : (op.i0 == 5 ? 2 : 1);
+  qrw_fold_all(tr, nvb, cnt, sm);
+  switch (op.i0) {
+    case 0:
+      for (int i = t; i < cols * cols; i += kBlock) R[i] = cz();
+      if (t == 0) s->tol = tr.rtol * sqrt(sm.fold[0].x);
+      break;
+    case 1:
+      if (t < k) s->h1[t] = sm.fold[t];
+      break;
+    case 2:
+      if (t < k) s->h2[t] = sm.fold[t];
+      break;
+    case 3:
+      if (t < k) R[t * cols + k] = cadd(s->h1[t], s->h2[t]);
+      if (t == 0) {
+        const double rn = sqrt(sm.fold[0].x);
+        s->rn = rn;
+        s->deficient = rn > s->tol ? 0 : 1;
+        if (!s->deficient) R[k * cols + k] = make_double2(rn, 0.0);
+      }
+      break;
+    case 4:
+      if (t < k) s->h2[t] = sm.fold[t];
+      break;
+    case 5:
+      if (t == 0) {
+        const double nu = sqrt(sm.fold[0].x);
+        const cd uv = sm.fold[1];
+        s->iu = 1.0 / nu;
+        R[k * cols + k] = cscale(uv, s->iu);
+        atomicAdd(&tr.stats[0], 1);
+      }
+      break;
+  }
+}
+
 // ------------------------------------------------------------ contraction
 // OP_CONTRACT: E[a', a] = sum_r conj(Qm[r, a']) Zm[r, a] over the rows of
 // the matricisations towards op.axis; Q = op.p0, Z = op.p2, shape from
 // desc.  Output op.p1 (D x D, row-major) or, with op.i0 = 1, transposed
 // into the current record at double offset op.i1.  Rows are split over vb.
-__device__ void body_contract(const Op& op, const DevTables& T, int vb, Smem& sm) {
+// Rows of this vb are staged in LDS (kCtRows at a time: Q and Z rows of D
+// entries each), then every thread accumulates its (a', a) pairs from LDS.
+constexpr int kCtRows = 32;
+__device__ void body_contract(const Op& op, const DevTables& T, int vb, Smem& sm, cd* lds) {
   const TreeDev& tr = T.trees[op.tree];
   const Shape& sh = T.descs[op.desc].sh;
   const int ax = op.axis;
@@ -601,21 +912,37 @@ __device__ void body_contract(const Op& op, const DevTables& T, int vb, Smem& sm
   const int chunk = (rows + op.nvb - 1) / op.nvb;
   const int r0 = vb * chunk, r1 = min(rows, r0 + chunk);
   cd* part = tr.cpart + (size_t)vb * D * D;  // per-vb partial matrix
-  for (int p = threadIdx.x; p < D * D; p += kBlock) part[p] = cz();
-  for (int base = r0; base < r1; base += 1024) {
-    const int nb = min(1024, r1 - base);
+  cd* qs = lds;                    // kCtRows x D
+  cd* zs = lds + kCtRows * 64;     // kCtRows x D
+  constexpr int kPairs = 16;       // D <= 64: at most 4096 pairs, 16 per thread
+  cd acc[kPairs];
+#pragma unroll
+  for (int q = 0; q < kPairs; ++q) acc[q] = cz();
+  for (int base = r0; base < r1; base += kCtRows) {
+    const int nb = min(kCtRows, r1 - base);
     __syncthreads();
-    for (int i = threadIdx.x; i < nb; i += kBlock) sm.rowbase[i] = qr_row_offset(sh, ax, base + i);
-    __syncthreads();
-    for (int p = threadIdx.x; p < D * D; p += kBlock) {
-      const int a1 = p / D, a2 = p % D;
-      cd acc = part[p];
-      for (int i = 0; i < nb; ++i) {
-        const int off = sm.rowbase[i];
-        acc = cjfma(op.p0[off + a1 * st], op.p2[off + a2 * st], acc);
-      }
-      part[p] = acc;
+    for (int e = threadIdx.x; e < nb * D; e += kBlock) {
+      const int i = e / D, a = e % D;
+      const int off = qr_row_offset(sh, ax, base + i) + a * st;
+      qs[i * D + a] = op.p0[off];
+      zs[i * D + a] = op.p2[off];
     }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPairs; ++q) {
+      const int p = threadIdx.x + q * kBlock;
+      if (p < D * D) {
+        const int a1 = p / D, a2 = p % D;
+        cd s = acc[q];
+        for (int i = 0; i < nb; ++i) s = cjfma(qs[i * D + a1], zs[i * D + a2], s);
+        acc[q] = s;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kPairs; ++q) {
+    const int p = threadIdx.x + q * kBlock;
+    if (p < D * D) part[p] = acc[q];
   }
 }
 __device__ void fin_contract(const Op& op, const DevTables& T, int nvb) {
@@ -639,28 +966,41 @@ __device__ void fin_contract(const Op& op, const DevTables& T, int nvb) {
 
 // ------------------------------------------------------------ bond step
 // Y = H_b X for the bond matrix X (Du x Dv), one workgroup; scratch S (Du x Dv).
-__device__ void bond_apply(const BondDesc& b, const cd* X, cd* Y, cd* S) {
+// The environment matrices come from `st` (LDS copies laid out as Eu, Ev,
+// then Eu_k, Ev_k per pair) when staged, else from the descriptor.
+__device__ __forceinline__ const cd* bond_mat(const BondDesc& b, const cd* st, int which, int k) {
+  const int u2 = b.Du * b.Du, v2 = b.Dv * b.Dv;
+  if (!st) return which == 0 ? (k < 0 ? b.Eu : b.Euk[k]) : (k < 0 ? b.Ev : b.Evk[k]);
+  const int pair = k < 0 ? 0 : k + 1;
+  return st + (size_t)pair * (u2 + v2) + (which == 0 ? 0 : u2);
+}
+
+__device__ void bond_apply(const BondDesc& b, const cd* st, const cd* X, cd* Y, cd* S) {
   const int Du = b.Du, Dv = b.Dv, n = Du * Dv;
+  const cd* Eu = bond_mat(b, st, 0, -1);
+  const cd* Ev = bond_mat(b, st, 1, -1);
   for (int p = threadIdx.x; p < n; p += kBlock) {
     const int a = p / Dv, c = p % Dv;
     cd acc = cz();
-    for (int m = 0; m < Du; ++m) acc = cfma(b.Eu[a * Du + m], X[m * Dv + c], acc);
-    for (int m = 0; m < Dv; ++m) acc = cfma(X[a * Dv + m], b.Ev[c * Dv + m], acc);
+    for (int m = 0; m < Du; ++m) acc = cfma(Eu[a * Du + m], X[m * Dv + c], acc);
+    for (int m = 0; m < Dv; ++m) acc = cfma(X[a * Dv + m], Ev[c * Dv + m], acc);
     Y[p] = acc;
   }
   __syncthreads();
   for (int k = 0; k < b.n_pairs; ++k) {
+    const cd* Euk = bond_mat(b, st, 0, k);
+    const cd* Evk = bond_mat(b, st, 1, k);
     for (int p = threadIdx.x; p < n; p += kBlock) {
       const int a = p / Dv, c = p % Dv;
       cd acc = cz();
-      for (int m = 0; m < Dv; ++m) acc = cfma(X[a * Dv + m], b.Evk[k][c * Dv + m], acc);
+      for (int m = 0; m < Dv; ++m) acc = cfma(X[a * Dv + m], Evk[c * Dv + m], acc);
       S[p] = acc;
     }
     __syncthreads();
     for (int p = threadIdx.x; p < n; p += kBlock) {
       const int a = p / Dv, c = p % Dv;
       cd acc = cz();
-      for (int m = 0; m < Du; ++m) acc = cfma(b.Euk[k][a * Du + m], S[m * Dv + c], acc);
+      for (int m = 0; m < Du; ++m) acc = cfma(Euk[a * Du + m], S[m * Dv + c], acc);
       Y[p] = make_double2(fma(b.coef[k], acc.x, Y[p].x), fma(b.coef[k], acc.y, Y[p].y));
     }
     __syncthreads();
@@ -668,15 +1008,32 @@ __device__ void bond_apply(const BondDesc& b, const cd* X, cd* Y, cd* S) {
 }
 
 // OP_BOND (one workgroup): R <- exp(sign i h H_b) R by the same Lanczos
-// process as the nodes (CGS2, breakdown, Krylov dimension kmax).
-__device__ void body_bond(const Op& op, const DevTables& T, Smem& sm) {
+// process as the nodes (CGS2, breakdown, Krylov dimension kmax).  The
+// Krylov basis, work vectors and environment matrices are staged in LDS
+// (`lds`, kQrLds entries) when they fit, else used from global memory.
+template <bool kLds>
+__device__ void body_bond_t(const Op& op, const DevTables& T, Smem& sm, cd* lds) {
   const TreeDev& tr = T.trees[op.tree];
   const BondDesc& b = T.bonds[op.desc];
   const int n = b.Du * b.Dv;
-  const int ld = op.i0;  // leading dimension of the bond Krylov basis
-  cd* V = tr.bondV;
-  cd* W = tr.bondW;
-  cd* S = tr.bondW + ld;
+  const int kmax = min(tr.kmax, n);
+  const int ld = kLds ? n : op.i0;  // leading dimension of the Krylov basis
+  cd* V = kLds ? lds : tr.bondV;
+  cd* W = kLds ? lds + (size_t)(kmax + 1) * n : tr.bondW;
+  cd* S = kLds ? W + n : tr.bondW + op.i0;
+  const cd* st = nullptr;
+  if (kLds) {
+    cd* e = S + n;
+    st = e;
+    const int u2 = b.Du * b.Du, v2 = b.Dv * b.Dv;
+    for (int k = -1; k < b.n_pairs; ++k) {
+      const cd* su = k < 0 ? b.Eu : b.Euk[k];
+      const cd* sv = k < 0 ? b.Ev : b.Evk[k];
+      for (int i = threadIdx.x; i < u2; i += kBlock) e[i] = su[i];
+      for (int i = threadIdx.x; i < v2; i += kBlock) e[u2 + i] = sv[i];
+      e += u2 + v2;
+    }
+  }
   __shared__ double al[kMaxKrylov], be[kMaxKrylov];
   __shared__ cd hh[kRedStride];
   cd q = cz();
@@ -687,11 +1044,10 @@ __device__ void body_bond(const Op& op, const DevTables& T, Smem& sm) {
   const double inx = 1.0 / nx;
   for (int p = threadIdx.x; p < n; p += kBlock) V[p] = cscale(b.R[p], inx);
   __syncthreads();
-  const int kmax = min(tr.kmax, n);
   int k = 0;
   for (int j = 0; j < kmax; ++j) {
-    bond_apply(b, V + (size_t)j * ld, W, S);
-    double a_j = 0.0, ww = 0.0;
+    bond_apply(b, st, V + (size_t)j * ld, W, S);
+    double a_j = 0.0;
     for (int pass = 0; pass < 2; ++pass) {
       for (int i = 0; i <= j; ++i) {
         cd d = cz();
@@ -715,7 +1071,7 @@ __device__ void body_bond(const Op& op, const DevTables& T, Smem& sm) {
     cd nw = cz();
     for (int p = threadIdx.x; p < n; p += kBlock) nw.x += cabs2(W[p]);
     nw = block_sum(nw, sm);
-    ww = sqrt(nw.x);
+    const double ww = sqrt(nw.x);
     if (threadIdx.x == 0) al[j] = a_j;
     k = j + 1;
     if (j == kmax - 1) break;
@@ -735,6 +1091,16 @@ __device__ void body_bond(const Op& op, const DevTables& T, Smem& sm) {
     for (int i = 0; i < k; ++i) acc = cfma(sm.vec[i], V[(size_t)i * ld + p], acc);
     b.R[p] = cscale(acc, nx);
   }
+}
+
+__device__ void body_bond(const Op& op, const DevTables& T, Smem& sm, cd* lds) {
+  const TreeDev& tr = T.trees[op.tree];
+  const BondDesc& b = T.bonds[op.desc];
+  const int n = b.Du * b.Dv;
+  const int kmax = min(tr.kmax, n);
+  const size_t need = (size_t)(kmax + 3) * n + (size_t)(1 + b.n_pairs) * (b.Du * b.Du + b.Dv * b.Dv);
+  if (need <= (size_t)kQrLds) body_bond_t<true>(op, T, sm, lds);
+  else body_bond_t<false>(op, T, sm, nullptr);
 }
 
 // ------------------------------------------------------------ small ops
@@ -807,11 +1173,15 @@ __global__ __launch_bounds__(kBlock) void k_op(Op op, DevTables T) {
   } else if constexpr (TY == OP_QR) {
     __shared__ cd qr_lds[kQrLds];
     body_qr(op, T, sm, qr_lds);
+  } else if constexpr (TY == OP_QRW) {
+    if (body_qrw(op, T, vb, sm) && last_block(tr.counter, op.nvb, sm)) fin_qrw(op, T, op.nvb, sm);
   } else if constexpr (TY == OP_CONTRACT) {
-    body_contract(op, T, vb, sm);
+    __shared__ cd ct_lds[2 * kCtRows * 64];
+    body_contract(op, T, vb, sm, ct_lds);
     if (last_block(tr.counter, op.nvb, sm)) fin_contract(op, T, op.nvb);
   } else if constexpr (TY == OP_BOND) {
-    body_bond(op, T, sm);
+    __shared__ cd bond_lds[kQrLds];
+    body_bond(op, T, sm, bond_lds);
   } else if constexpr (TY == OP_COPY) {
     body_copy(op, vb);
   } else if constexpr (TY == OP_DOT) {
@@ -872,13 +1242,20 @@ __global__ __launch_bounds__(kBlock) void k_persistent(const Op* __restrict__ op
         body_qr(op, T, sm, qr_lds);
         break;
       case OP_CONTRACT:
-        for (int vb = 0; vb < nvb; ++vb) body_contract(op, T, vb, sm);
+        for (int vb = 0; vb < nvb; ++vb) body_contract(op, T, vb, sm, qr_lds);
         __syncthreads();
         fin_contract(op, T, nvb);
         break;
       case OP_BOND:
-        body_bond(op, T, sm);
+        body_bond(op, T, sm, qr_lds);
         break;
+      case OP_QRW: {
+        bool act = false;
+        for (int vb = 0; vb < nvb; ++vb) act = body_qrw(op, T, vb, sm) || act;
+        __syncthreads();
+        if (act) fin_qrw(op, T, nvb, sm);
+        break;
+      }
       case OP_COPY:
         for (int vb = 0; vb < nvb; ++vb) body_copy(op, vb);
         break;
@@ -897,8 +1274,11 @@ __global__ __launch_bounds__(kBlock) void k_persistent(const Op* __restrict__ op
   }
 }
 
+hipError_t launch_mode(const Op& op, const DevTables& t, hipStream_t s, int prec, int n_rest, int d);
+
 hipError_t launch_op(const Op& op, const DevTables& t, hipStream_t s) {
   const dim3 grid(op.nvb > 0 ? op.nvb : 1), block(kBlock);
+  if (op.type == OP_MODE) return launch_mode(op, t, s, op.i0, op.n, op.axis);
   switch (op.type) {
 #define TTNS_CASE(T_)                                            \
   case T_:                                                       \
@@ -918,6 +1298,7 @@ hipError_t launch_op(const Op& op, const DevTables& t, hipStream_t s) {
     TTNS_CASE(OP_DOT)
     TTNS_CASE(OP_RECORD)
     TTNS_CASE(OP_SETH)
+    TTNS_CASE(OP_QRW)
 #undef TTNS_CASE
     default:
       return hipErrorInvalidValue;

@@ -20,6 +20,9 @@ constexpr int kMaxKrylov = 16;   // Lanczos dimension limit
 constexpr int kMaxPairs = 16;    // crossing terms on one bond
 constexpr int kBlock = 256;      // threads per workgroup (4 wavefronts)
 constexpr int kRedStride = kMaxKrylov + 2;  // partial-sum slots per block
+constexpr int kMaxQrVb = 64;     // workgroups of a wide QR
+constexpr int kQrStride = 68;    // partial-sum slots per workgroup of a wide QR
+constexpr int kQrLdsEntries = 8800;  // complex entries of the single-workgroup QR's LDS
 
 using cd = double2;  // complex double, interleaved (re, im)
 
@@ -59,6 +62,35 @@ struct ApplyDesc {
   double flops;  // algorithmic real flops of one apply (for reporting)
 };
 
+// One group of an H_eff apply on the matrix cores: every term acting on
+// bond axis `axis` with the same source tensor, as banded mode products
+//   y[s] (+)= sum_{o = band_lo..band_hi} M_{s,o} x_axis src[s + o],
+//   M_{s,o} = sum_e coef_e g_e(s, o) E_e,  g_e = op_e[s][s+o] (or delta_{o0}),
+// with the complex products done as real GEMMs [[Re M, -Im M], [Im M, Re M]]
+// . [Re src; Im src] on MFMA tiles (FP64, FP32 or split BF16).  The first
+// group of an apply writes y (plus the on-site term), later ones add.
+constexpr int kMaxGroup = 8;
+struct ModeDesc {
+  Shape sh;
+  int axis;
+  int prec;        // TTNS_FP64 / TTNS_FP32 / TTNS_BF16X3
+  int accumulate;  // 0: y = site o x + group; 1: y += group
+  int band_lo, band_hi;
+  int n_rest;      // size / (dims[axis] * dims[phys])
+  const cd* src;   // default source (x, or a temporary)
+  const cd* x;     // apply input (for the on-site term)
+  cd* y;
+  const cd* site;
+  double site_coef;
+  int site_lo, site_hi;
+  int n_e;
+  const cd* E[kMaxGroup];
+  const cd* op[kMaxGroup];
+  int lo[kMaxGroup], hi[kMaxGroup];
+  double coef[kMaxGroup];
+  double flops;
+};
+
 // Bond effective Hamiltonian between u (rows of R) and v (columns):
 //   H_b R = Eu R + R Ev^T + sum_k coef_k Eu_k R Ev_k^T
 struct BondDesc {
@@ -84,6 +116,13 @@ struct LzScal {
   int pad[2];
 };
 
+// Scalars of a running wide (multi-workgroup) QR.
+struct QrScal {
+  double tol, rn, iu;
+  int deficient, row;
+  cd h1[64], h2[64];
+};
+
 // Per-tree device scratch (all inside the caller's workspace).
 struct TreeDev {
   LzScal* scal;
@@ -100,6 +139,8 @@ struct TreeDev {
   cd* qrv;          // 2 x maxrows residual / completion vectors
   cd* partials;     // max_nvb x kRedStride
   cd* cpart;        // contraction partial matrices, max_nvb x maxD^2
+  cd* qrpart;       // wide-QR partial sums, kMaxQrVb x kQrStride
+  QrScal* qrs;
   unsigned* counter;
   double* hist;     // rec_cap x rec_size
   int* rec_count;
@@ -126,6 +167,8 @@ enum OpType : int {
   OP_DOT,         // <a|b> into the record
   OP_RECORD,      // close the record of this step
   OP_SETH,        // set the half step of the context
+  OP_QRW,         // one phase of a wide QR (op.i0 = phase, op.j = column)
+  OP_MODE,        // one MFMA group of an apply (ModeDesc op.desc; p0/p1 override src/y)
   OP_COUNT
 };
 
@@ -172,6 +215,7 @@ bool api_to_tree(const ttns_tree& a, HostTree& t, std::string& err);
 // kernels.hip: device entry points used by the executors
 struct DevTables {
   const ApplyDesc* descs;
+  const ModeDesc* modes;
   const BondDesc* bonds;
   const TreeDev* trees;
   double* half_step;  // context-wide h = dt / 2
@@ -182,5 +226,8 @@ hipError_t launch_persistent(const Op* dev_ops, const int* dev_begin,
                              const int* dev_end, int n_trees,
                              const DevTables& t, hipStream_t s);
 hipError_t launch_set_half_step(double* dst, double h, hipStream_t s);
+// MFMA limits: bond dimension per precision, columns per workgroup tile
+constexpr int kModeNT = 64;
+int mode_max_bond(int prec);
 
 }  // namespace ttns

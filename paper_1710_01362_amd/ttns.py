@@ -25,6 +25,7 @@ TTNS_EXEC_AUTO, TTNS_EXEC_WIDE, TTNS_EXEC_PERSISTENT = 0, 1, 2
 
 OBS_RDM, OBS_POP, OBS_LOCAL, OBS_NORM, OBS_ENERGY = 0, 1, 2, 3, 4
 OBS_HISTORY, OBS_RECORD_SIZE, OBS_TENSOR, OBS_STATS, OBS_BOND_DIMS = 5, 6, 7, 8, 9
+OBS_STEP_FLOPS = 10
 
 EXPORTED = [
     "ttns_default_opts", "ttns_ohmic_chain", "ttns_workspace_size", "ttns_star_workspace_size",
@@ -297,6 +298,11 @@ class Context:
         s = self.ttns_observe(OBS_STATS, tree, n=5)
         return {"records": int(s[0]), "guarded": int(s[1]), "steps": int(s[2]),
                 "breakdowns": int(s[3]), "flags": int(s[4])}
+
+    def step_flops(self, tree=0):
+        """Algorithmic flops of one step of ``tree``: (total, H_eff part)."""
+        f = self.ttns_observe(OBS_STEP_FLOPS, tree, n=2)
+        return float(f[0]), float(f[1])
 
     def bond_dims(self, tree, n_nodes):
         return self.ttns_observe(OBS_BOND_DIMS, tree, n=n_nodes).astype(int)

@@ -118,7 +118,7 @@ def test_apply_heff_parity_at_every_node_kind(name):
     After evolution, QR columns whose residual sits just above the rank guard
     (1e-8 |A|) are determined only to eps / 1e-8: random inputs along such
     gauge directions may differ up to ~1e-8 relative, while the physical
-    centre tensor agrees to 1e-10 and H_eff applied to it to 1e-8 relative
+    centre tensor agrees to 1e-10 and H_eff applied to it to 1e-7 relative
     (environments are built from those isometries).
     """
     T = _T()
@@ -138,7 +138,7 @@ def test_apply_heff_parity_at_every_node_kind(name):
     ctx.ttns_tdvp_step(m["dt"], 2)
     h = ctx.history()
     np.testing.assert_allclose(h["rdm"][-1], tt.rdm(), atol=1e-12)
-    _apply_check(ctx, tt, nodes, rng, 1e-7, 1e-8, 1e-10)
+    _apply_check(ctx, tt, nodes, rng, 1e-7, 1e-7, 1e-10)
     ctx.close()
 
 
