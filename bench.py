@@ -1,15 +1,19 @@
-"""Benchmark: TDVP site updates/s of the FP64 TTNS one-site TDVP step on one
+"""Benchmark: TDVP site updates/s of the TTNS one-site TDVP step on one
 MI355X, with the roofline of the dominant kernel and the CPU oracle beside it.
 
 A step is one second-order TDVP step of the whole tree (pre-order sweep with
 h = dt/2 and its adjoint post-order sweep: every node evolved, every bond
 evolved backward, the QR / environment / absorb work of every centre move,
-and the observables of the step), i.e. 2 * n_nodes site updates.
+and the observables of the step), i.e. 2 * n_nodes site updates per tree.
 
 Default workload: the five-level vibronic tree (4 chains x 40 sites, local
-dimension 20, bond dimension 20, dt = 0.5 fs), synthetic seeded parameters.
+dimension 20, bond dimension 20, dt = 0.5 fs), synthetic seeded parameters,
+FP64.  Timed region: K graph-replayed steps with the inputs resident in HBM.
+The per-kernel figures come from extra profiled steps of the same run (one
+launch at a time, HIP events around each launch on the library's stream).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                    [--precision fp64|fp32|bf16x3]
 """
 import argparse
 import json
@@ -24,26 +28,32 @@ sys.path.insert(0, ROOT)
 
 import workloads as W  # noqa: E402
 
-PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 (vector and matrix): 256 CU x 128 flop/clk x 2.4 GHz
+# MI355X published peaks
+PEAK = {"fp64": 78.6, "fp32_mfma": 157.3, "bf16_mfma": 2500.0, "hbm_gbs": 8000.0}
 
 WORKLOADS = {
-    "vibronic": (W.vibronic_reference,
+    "vibronic": (lambda: [W.vibronic_reference()],
                  "five-level vibronic tree: 4 Ohmic chains x 40 sites, d=20, D=20, wc=0.2 eV, "
                  "dt=0.5 fs, seed 2"),
-    "spin_boson": (W.spin_boson_reference,
+    "spin_boson": (lambda: [W.spin_boson_reference()],
                    "spin-boson: 1 Ohmic chain x 10 sites, d=10, D=8, alpha=0.1, dt=0.05"),
-    "large_er": (W.large_tree,
+    "large_er": (lambda: [W.large_tree()],
                  "five-level root, ER tree of 6 nodes, 8 chains x 100 sites, d=30, D=48, seed 4"),
+    "ensemble": (lambda: W.ensemble(),
+                 "256 uneven spin-boson trees (L 20..120, d 8/16/24, D 8/16/32), one persistent "
+                 "launch per step, seed 3"),
 }
+PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 
 
-def cpu_baseline(model, seconds=20.0):
+def cpu_baseline(models, seconds=20.0):
     """The oracle, timed on the host cores on a bounded sample of the same
-    workload: whole TDVP steps until ~``seconds`` of CPU work."""
+    workload: whole TDVP steps (of the first tree) until ~``seconds``."""
     from threadpoolctl import threadpool_info
     from oracle.model import build_tree
     from oracle.ttns import TTNS
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    model = models[0]
     tt = TTNS(build_tree(model), krylov=model.get("krylov", 12))
     steps = 0
     t0 = time.perf_counter()
@@ -55,8 +65,32 @@ def cpu_baseline(model, seconds=20.0):
             break
     upd = 2 * tt.n * steps
     return {"value": upd / el, "unit": "site updates/s", "cores": int(threads), "kind": "oracle",
-            "sample": "%d full TDVP step(s) of the same workload (%d site updates) in %.1f s"
+            "sample": "%d full TDVP step(s) of tree 0 of the same workload (%d site updates) in %.1f s"
                       % (steps, upd, el)}
+
+
+def roofline_of(kid, k, prec):
+    """Bound, achieved and peak of one kernel from its live totals."""
+    secs = k["ms"] * 1e-3
+    fl, by = k["flops"], k["bytes"]
+    if kid in (16, 17, 18):  # matrix-core groups
+        if kid == 16:
+            peak, unit, achieved = PEAK["fp64"], "TFLOP/s", fl / secs / 1e12
+        elif kid == 17:
+            peak, unit, achieved = PEAK["fp32_mfma"], "TFLOP/s", fl / secs / 1e12
+        else:  # three bf16 products per real product
+            peak, unit, achieved = PEAK["bf16_mfma"], "TFLOP/s", 3 * fl / secs / 1e12
+        bound = "mfma"
+    else:
+        intensity = fl / by if by else 0.0
+        if intensity >= PEAK["fp64"] * 1e12 / (PEAK["hbm_gbs"] * 1e9):
+            bound, peak, unit, achieved = "alu", PEAK["fp64"], "TFLOP/s", fl / secs / 1e12
+        else:
+            bound, peak, unit, achieved = "hbm", PEAK["hbm_gbs"], "GB/s", by / secs / 1e9
+    return {"bound": bound, "kernel": k["name"], "achieved": achieved, "peak": peak, "unit": unit,
+            "frac": achieved / peak, "traffic": None, "avg_launch_ms": k["ms"] / k["launches"],
+            "launches": k["launches"], "flops_per_launch": fl / k["launches"],
+            "bytes_per_launch": by / k["launches"], "share_of_step_time": None}
 
 
 def main():
@@ -65,6 +99,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="vibronic", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp64", choices=sorted(PREC))
     ap.add_argument("--profile-steps", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -78,34 +113,22 @@ def main():
     from paper_1710_01362_amd import ttns as T
 
     make, desc = WORKLOADS[args.workload]
-    model = make()
-    n_nodes = W.node_count(model)
-    upd_per_step = 2 * n_nodes
+    models = make()
+    upd_per_step = sum(2 * W.node_count(m) for m in models)
     total = args.warmup + args.steps + args.profile_steps + 1
-    ctx = T.Context([model], opts=T.default_opts(record_capacity=total + 1))
-    dt = model["dt"]
+    ctx = T.Context(models, opts=T.default_opts(record_capacity=total + 1,
+                                                precision=PREC[args.precision]))
+    dt = models[0]["dt"]
+    persistent = len(models) > 1
 
     ctx.ttns_tdvp_step(dt, args.warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ctx.ttns_tdvp_step(dt, args.steps)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    el = t1 - t0
+    el = time.perf_counter() - t0
+    step_flops = sum(ctx.step_flops(i)[0] for i in range(len(models)))
 
-    # dominant kernel (the H_eff contraction inside Lanczos): HIP events
-    # around each of its launches over extra steps of the same run
-    ctx.profile(True)
-    ctx.ttns_tdvp_step(dt, args.profile_steps)
-    prof = ctx.profile_read(reset=True)
-    ctx.profile(False)
-    torch.cuda.synchronize()
-    h = ctx.history()
-    drift = {"norm": float(np.abs(h["norm"] - 1).max()),
-             "energy": float(np.abs(h["energy"] - h["energy"][0]).max())}
-    ctx.close()
-
-    achieved = prof["flops_per_launch"] / (prof["avg_ms"] * 1e-3) / 1e12 if prof["avg_ms"] > 0 else 0.0
     out = {
         "metric": "TDVP site updates/s + % MFMA peak vs FP64 plain at ≤1e-6 population error",
         "value": upd_per_step * args.steps / el,
@@ -117,19 +140,45 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": {"fp64": "f64", "fp32": "f32 contractions (f64 elsewhere)",
+                  "bf16x3": "split-bf16 contractions (f64 elsewhere)"}[args.precision],
         "data": "synthetic",
-        "config": {"workload": desc, "nodes": n_nodes, "site_updates_per_step": upd_per_step,
-                   "krylov": model["krylov"], "executor": "wide kernels in one HIP graph per step"},
-        "roofline": {"bound": "alu", "kernel": "k_op<OP_APPLY_LZ> (H_eff apply in Lanczos)",
-                     "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                     "avg_launch_ms": prof["avg_ms"], "launches": prof["launches"],
-                     "flops_per_launch": prof["flops_per_launch"]},
-        "drift": drift,
+        "config": {"workload": desc, "trees": len(models), "site_updates_per_step": upd_per_step,
+                   "krylov": models[0]["krylov"],
+                   "executor": "one persistent workgroup per tree" if persistent
+                   else "one kernel per operation, replayed as a HIP graph"},
+        "step_tflops": step_flops / (el / args.steps) / 1e12,
     }
+    if persistent:
+        # one kernel per step: its own duration is the step time
+        out["roofline"] = {"bound": "alu", "kernel": "ttns::k_persistent (whole step)",
+                           "achieved": out["step_tflops"], "peak": PEAK["fp64"], "unit": "TFLOP/s",
+                           "frac": out["step_tflops"] / PEAK["fp64"], "traffic": None,
+                           "avg_launch_ms": out["ms_per_step"], "flops_per_launch": step_flops}
+    else:
+        ctx.profile(True)
+        ctx.ttns_tdvp_step(dt, args.profile_steps)
+        kern = ctx.profile_kernels()
+        ctx.profile(False)
+        tot = sum(k["ms"] for k in kern.values())
+        dom = max(kern, key=lambda k: kern[k]["ms"])
+        out["roofline"] = roofline_of(dom, kern[dom], args.precision)
+        out["roofline"]["share_of_step_time"] = kern[dom]["ms"] / tot
+        heff = [kid for kid in (1, 16, 17, 18) if kid in kern]
+        out["heff_rooflines"] = []
+        for kid in heff:
+            r = roofline_of(kid, kern[kid], args.precision)
+            r["share_of_step_time"] = kern[kid]["ms"] / tot
+            out["heff_rooflines"].append(r)
+        out["kernel_time_share"] = {kern[k]["name"]: round(kern[k]["ms"] / tot, 4)
+                                    for k in sorted(kern, key=lambda k: -kern[k]["ms"])}
+    torch.cuda.synchronize()
+    h = ctx.history(0)
+    out["drift"] = {"norm": float(np.abs(h["norm"] - 1).max()),
+                    "energy": float(np.abs(h["energy"] - h["energy"][0]).max())}
+    ctx.close()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(model, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(models, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

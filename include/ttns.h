@@ -181,12 +181,41 @@ int ttns_tdvp_step(ttns_ctx *ctx, double dt, int32_t n_steps);
 int ttns_observe(ttns_ctx *ctx, int32_t kind, int32_t tree, int32_t index,
                  double *host_out, size_t n_out);
 
-/* Average device time (ms) per launch of the H_eff contraction kernel over
- * the launches timed since the last call with reset != 0 (events around
- * every launch of that kernel; enabled by ttns_profile(ctx, 1)). */
+/* Kernels, for profiling.  Ids 0..15 are the one-operation kernels (their
+ * device symbols are ttns::k_op<id>), 16..18 the matrix-core H_eff group
+ * kernels ttns::k_mode<precision> for FP64, FP32 and BF16X3. */
+#define TTNS_K_APPLY 0      /* scalar operator apply (environments, absorb)  */
+#define TTNS_K_HEFF_LZ 1    /* scalar H_eff apply + Lanczos dots             */
+#define TTNS_K_NORM 2
+#define TTNS_K_SCALE 3
+#define TTNS_K_ORTH1 4      /* Gram-Schmidt pass 1                           */
+#define TTNS_K_ORTH2 5      /* Gram-Schmidt pass 2, next Krylov vector       */
+#define TTNS_K_COMBINE 6    /* Krylov exponential and combination            */
+#define TTNS_K_QR 7         /* guarded QR, one workgroup                     */
+#define TTNS_K_CONTRACT 8   /* environment contraction                       */
+#define TTNS_K_BOND 9       /* backward bond exponential                     */
+#define TTNS_K_COPY 10
+#define TTNS_K_DOT 11
+#define TTNS_K_RECORD 12
+#define TTNS_K_QR_WIDE 14   /* guarded QR, one phase over many workgroups    */
+#define TTNS_K_MODE_FP64 16 /* matrix-core H_eff group                       */
+#define TTNS_K_MODE_FP32 17
+#define TTNS_K_MODE_BF16X3 18
+#define TTNS_K_COUNT 19
+
+/* With enable != 0, ttns_tdvp_step runs its kernels one by one (no graph)
+ * with a pair of HIP events around every launch on the context's stream.
+ * ttns_profile_read: average device time (ms) per launch, launches and
+ * algorithmic flops per launch of the H_eff contraction (TTNS_K_HEFF_LZ and
+ * TTNS_K_MODE_*) since the last reset.  ttns_profile_kernel: totals of one
+ * kernel since the last reset (ms, launches, algorithmic flops, algorithmic
+ * bytes: every operand read once and every result written once, 16 bytes per
+ * complex entry). */
 int ttns_profile(ttns_ctx *ctx, int32_t enable);
 int ttns_profile_read(ttns_ctx *ctx, int32_t reset, double *avg_ms,
                       int64_t *launches, double *flops_per_launch);
+int ttns_profile_kernel(ttns_ctx *ctx, int32_t kernel, double *total_ms,
+                        int64_t *launches, double *flops, double *bytes);
 
 int ttns_destroy(ttns_ctx *ctx);
 const char *ttns_last_error(void);

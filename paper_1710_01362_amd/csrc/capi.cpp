@@ -211,7 +211,14 @@ struct ttns_ctx {
   bool profile = false;
   double prof_ms = 0.0, prof_flops = 0.0;
   int64_t prof_n = 0;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
+  struct Pending {
+    hipEvent_t e0, e1;
+    int cls;
+    double flops, bytes;
+  };
+  std::vector<Pending> ev_pool;
+  double cls_ms[TTNS_K_COUNT] = {0}, cls_flops[TTNS_K_COUNT] = {0}, cls_bytes[TTNS_K_COUNT] = {0};
+  int64_t cls_n[TTNS_K_COUNT] = {0};
   double last_h = -1e300;
   int scratch_desc = 0;  // first of the descriptor slots ttns_apply_heff rewrites
   std::vector<double> step_flops, heff_flops;  // per tree, algorithmic
@@ -1072,21 +1079,91 @@ struct Builder {
 };
 
 // ------------------------------------------------------------------ execution
+// Kernel id, algorithmic flops and bytes of one launch (for profiling).
+void op_cost(const ttns_ctx& c, const Op& o, int& kid, double& flops, double& bytes) {
+  const double C = 16.0;
+  flops = bytes = 0.0;
+  kid = o.type == OP_MODE ? TTNS_K_MODE_FP64 + o.i0 : o.type;
+  switch (o.type) {
+    case OP_APPLY_LZ: {
+      const ApplyDesc& d = c.descs[o.desc];
+      if (o.i0) {  // only the dots of an MFMA apply
+        flops = 8.0 * d.sh.size * (o.j + 2);
+        bytes = C * d.sh.size * (o.j + 2);
+      } else {
+        flops = d.flops + 8.0 * d.sh.size * (o.j + 2);
+        bytes = C * d.sh.size * (o.j + 3);
+      }
+      return;
+    }
+    case OP_MODE: {
+      const ModeDesc& m = c.modes[o.desc];
+      const double D = m.sh.dims[m.axis];
+      flops = m.flops;
+      bytes = C * m.sh.size * ((m.band_hi - m.band_lo + 1) + 1 + m.accumulate) + C * D * D * m.n_e;
+      return;
+    }
+    case OP_NORM:
+    case OP_SCALE:
+    case OP_COMBINE:
+    case OP_ORTH1:
+    case OP_ORTH2: {
+      const double n = o.n, k = o.type == OP_COMBINE ? c.opts.krylov_dim : o.j + 1;
+      flops = 8.0 * n * (o.type == OP_ORTH1 ? 2 * k : k);
+      bytes = C * n * (k + 1);
+      return;
+    }
+    case OP_QR:
+    case OP_QRW: {
+      if (o.type == OP_QRW && o.i0 != 0) return;  // counted once per QR
+      const Shape& sh = c.descs[o.desc].sh;
+      const double cols = sh.dims[o.axis], rows = sh.size / cols;
+      flops = 16.0 * rows * cols * cols;
+      bytes = 2.0 * C * rows * cols;
+      return;
+    }
+    case OP_CONTRACT: {
+      const Shape& sh = c.descs[o.desc].sh;
+      const double D = sh.dims[o.axis];
+      flops = 8.0 * sh.size * D;
+      bytes = 2.0 * C * sh.size + C * D * D;
+      return;
+    }
+    case OP_APPLY: {
+      const ApplyDesc& d = c.descs[o.desc];
+      flops = d.flops;
+      bytes = 2.0 * C * d.sh.size;
+      return;
+    }
+    case OP_BOND: {
+      const BondDesc& b = c.bonds[o.desc];
+      const double Du = b.Du, Dv = b.Dv;
+      flops = 8.0 * c.opts.krylov_dim * (Du * Du * Dv + Du * Dv * Dv) * (1 + b.n_pairs);
+      bytes = C * (2.0 * Du * Dv + (Du * Du + Dv * Dv) * (1 + b.n_pairs));
+      return;
+    }
+    case OP_COPY:
+      bytes = 2.0 * C * o.n;
+      return;
+    default:
+      return;
+  }
+}
+
 int run_ops(ttns_ctx& c, const std::vector<Op>& ops) {
   for (const Op& o : ops) {
-    const bool prof = c.profile && o.type == OP_APPLY_LZ;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (prof) {
+    if (c.profile) {
       HIPCHK(hipEventCreate(&e0));
       HIPCHK(hipEventCreate(&e1));
       HIPCHK(hipEventRecord(e0, c.stream));
     }
     HIPCHK(launch_op(o, c.tables, c.stream));
-    if (prof) {
+    if (c.profile) {
       HIPCHK(hipEventRecord(e1, c.stream));
-      c.ev_pool.push_back({e0, e1});
-      c.prof_flops += c.descs[o.desc].flops;
-      c.prof_n += 1;
+      ttns_ctx::Pending p{e0, e1, 0, 0.0, 0.0};
+      op_cost(c, o, p.cls, p.flops, p.bytes);
+      c.ev_pool.push_back(p);
     }
   }
   return TTNS_OK;
@@ -1097,10 +1174,13 @@ int drain_profile(ttns_ctx& c) {
   HIPCHK(hipStreamSynchronize(c.stream));
   for (auto& pr : c.ev_pool) {
     float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
-    c.prof_ms += ms;
-    (void)hipEventDestroy(pr.first);
-    (void)hipEventDestroy(pr.second);
+    HIPCHK(hipEventElapsedTime(&ms, pr.e0, pr.e1));
+    c.cls_ms[pr.cls] += ms;
+    c.cls_flops[pr.cls] += pr.flops;
+    c.cls_bytes[pr.cls] += pr.bytes;
+    c.cls_n[pr.cls] += 1;
+    (void)hipEventDestroy(pr.e0);
+    (void)hipEventDestroy(pr.e1);
   }
   c.ev_pool.clear();
   return TTNS_OK;
@@ -1756,14 +1836,33 @@ int ttns_profile_read(ttns_ctx* c, int32_t reset, double* avg_ms, int64_t* launc
   if (!c) return fail(TTNS_EINVAL, "ttns_profile_read: null context");
   int rc = drain_profile(*c);
   if (rc) return rc;
-  if (avg_ms) *avg_ms = c->prof_n ? c->prof_ms / c->prof_n : 0.0;
-  if (launches) *launches = c->prof_n;
-  if (flops) *flops = c->prof_n ? c->prof_flops / c->prof_n : 0.0;
-  if (reset) {
-    c->prof_ms = 0.0;
-    c->prof_n = 0;
-    c->prof_flops = 0.0;
+  double ms = 0.0, fl = 0.0;
+  int64_t n = 0;
+  for (int k : {(int)TTNS_K_HEFF_LZ, (int)TTNS_K_MODE_FP64, (int)TTNS_K_MODE_FP32, (int)TTNS_K_MODE_BF16X3}) {
+    ms += c->cls_ms[k];
+    fl += c->cls_flops[k];
+    n += c->cls_n[k];
   }
+  if (avg_ms) *avg_ms = n ? ms / n : 0.0;
+  if (launches) *launches = n;
+  if (flops) *flops = n ? fl / n : 0.0;
+  if (reset)
+    for (int i = 0; i < TTNS_K_COUNT; ++i) {
+      c->cls_ms[i] = c->cls_flops[i] = c->cls_bytes[i] = 0.0;
+      c->cls_n[i] = 0;
+    }
+  return TTNS_OK;
+}
+
+int ttns_profile_kernel(ttns_ctx* c, int32_t kernel, double* total_ms, int64_t* launches, double* flops,
+                        double* bytes) {
+  if (!c || kernel < 0 || kernel >= TTNS_K_COUNT) return fail(TTNS_EINVAL, "ttns_profile_kernel: bad arguments");
+  int rc = drain_profile(*c);
+  if (rc) return rc;
+  if (total_ms) *total_ms = c->cls_ms[kernel];
+  if (launches) *launches = c->cls_n[kernel];
+  if (flops) *flops = c->cls_flops[kernel];
+  if (bytes) *bytes = c->cls_bytes[kernel];
   return TTNS_OK;
 }
 

@@ -30,8 +30,17 @@ OBS_STEP_FLOPS = 10
 EXPORTED = [
     "ttns_default_opts", "ttns_ohmic_chain", "ttns_workspace_size", "ttns_star_workspace_size",
     "ttns_build", "ttns_star_build", "ttns_apply_heff", "ttns_tdvp_step", "ttns_observe",
-    "ttns_profile", "ttns_profile_read", "ttns_destroy", "ttns_last_error",
+    "ttns_profile", "ttns_profile_read", "ttns_profile_kernel", "ttns_destroy", "ttns_last_error",
 ]
+# kernel ids (include/ttns.h) -> device symbol
+KERNELS = {0: "ttns::k_op<0> (scalar apply)", 1: "ttns::k_op<1> (scalar H_eff + Lanczos dots)",
+           2: "ttns::k_op<2> (norm)", 3: "ttns::k_op<3> (scale)", 4: "ttns::k_op<4> (Gram-Schmidt 1)",
+           5: "ttns::k_op<5> (Gram-Schmidt 2)", 6: "ttns::k_op<6> (Krylov exp + combine)",
+           7: "ttns::k_op<7> (guarded QR)", 8: "ttns::k_op<8> (environment contraction)",
+           9: "ttns::k_op<9> (bond exponential)", 10: "ttns::k_op<10> (copy)", 11: "ttns::k_op<11> (dot)",
+           12: "ttns::k_op<12> (record)", 14: "ttns::k_op<14> (wide QR phase)",
+           16: "ttns::k_mode<0> (FP64 MFMA H_eff group)", 17: "ttns::k_mode<1> (FP32 MFMA H_eff group)",
+           18: "ttns::k_mode<2> (BF16x3 MFMA H_eff group)"}
 
 
 class c64(C.Structure):
@@ -98,6 +107,7 @@ def lib():
         L.ttns_observe.argtypes = [P, I, I, I, C.POINTER(D), S]
         L.ttns_profile.argtypes = [P, I]
         L.ttns_profile_read.argtypes = [P, I, C.POINTER(D), C.POINTER(C.c_int64), C.POINTER(D)]
+        L.ttns_profile_kernel.argtypes = [P, I, C.POINTER(D), C.POINTER(C.c_int64), C.POINTER(D), C.POINTER(D)]
         L.ttns_destroy.argtypes = [P]
         L.ttns_last_error.argtypes = []
         L.ttns_last_error.restype = C.c_char_p
@@ -309,6 +319,17 @@ class Context:
 
     def profile(self, enable=True):
         check(lib().ttns_profile(self.ctx, 1 if enable else 0))
+
+    def profile_kernels(self):
+        """Per kernel id: total ms, launches, algorithmic flops and bytes."""
+        out = {}
+        for kid, name in KERNELS.items():
+            ms, n, fl, by = C.c_double(), C.c_int64(), C.c_double(), C.c_double()
+            check(lib().ttns_profile_kernel(self.ctx, kid, C.byref(ms), C.byref(n), C.byref(fl), C.byref(by)))
+            if n.value:
+                out[kid] = {"name": name, "ms": ms.value, "launches": n.value, "flops": fl.value,
+                            "bytes": by.value}
+        return out
 
     def profile_read(self, reset=True):
         ms, n, fl = C.c_double(), C.c_int64(), C.c_double()
