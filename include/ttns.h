@@ -57,6 +57,12 @@ extern "C" {
 #define TTNS_EXEC_WIDE 1       /* each operation spread over many workgroups */
 #define TTNS_EXEC_PERSISTENT 2 /* one workgroup runs a whole tree's step     */
 
+/* option flags */
+#define TTNS_FLAG_MFMA_ALL 1u  /* matrix-core H_eff for every node whose bonds
+                                  fit the tiles; by default only nodes of at
+                                  least 16384 entries use it (smaller ones are
+                                  latency-bound and keep the scalar FP64 apply) */
+
 /* observables (ttns_observe kinds) */
 #define TTNS_OBS_RDM 0       /* root reduced density matrix, n x n complex:
                                 2 n^2 doubles (re, im), row-major           */
@@ -133,7 +139,7 @@ typedef struct {
   double rank_tol;           /* QR completion below tol*|A|_F (1e-8)        */
   int32_t record_capacity;   /* records kept on the device (>= 1)            */
   int32_t executor;          /* TTNS_EXEC_*                                  */
-  uint32_t flags;            /* reserved, 0                                  */
+  uint32_t flags;            /* TTNS_FLAG_* (0 by default)                   */
 } ttns_opts;
 
 typedef struct ttns_ctx ttns_ctx;

@@ -36,7 +36,9 @@ int fail(int code, const std::string& msg) {
 constexpr int PHYS = -1;
 constexpr int kMaxD = 64;       // QR keeps per-column scalars in shared arrays
 constexpr int kMaxContractVb = 64;
-constexpr int kMfmaMinSize = 16384;  // FP64 nodes this large use the matrix cores
+constexpr int kMfmaMinSize = 16384;  // nodes this large use the matrix cores
+constexpr size_t kGraphSegment = 8192;  // launches per captured graph
+constexpr int kQrOneGroupRows = 4096;   // tallest QR left to one workgroup
 
 // Channel of an environment: the block Hamiltonian (kind 0), one end of a
 // two-node term (kind 1: term k, end 0 = node_a / 1 = node_b) or a recorded
@@ -205,8 +207,11 @@ struct ttns_ctx {
   std::vector<Op> step_ops;        // wide program of one step (all trees)
   std::vector<int> tree_begin, tree_end;
   std::vector<Op> tree_prog;       // persistent program (per tree contiguous)
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
+  // one step as a sequence of captured graphs of at most kGraphSegment
+  // launches each (instantiation cost and host memory grow with the node
+  // count; a large tree's step holds hundreds of thousands of launches)
+  std::vector<hipGraph_t> graphs;
+  std::vector<hipGraphExec_t> gexecs;
   bool persistent = false;
   bool profile = false;
   double prof_ms = 0.0, prof_flops = 0.0;
@@ -635,7 +640,8 @@ struct Builder {
     const int prec = c.opts.precision;
     if (c.persistent) return false;  // the one-workgroup executor keeps the scalar apply
     const Shape& sh = t.shape[v];
-    if (prec == TTNS_FP64 && sh.size < kMfmaMinSize) return false;
+    if (sh.size < kMfmaMinSize && !(c.opts.flags & TTNS_FLAG_MFMA_ALL))
+      return false;  // small nodes: latency-bound, scalar FP64 apply
     const int maxD = mode_max_bond(prec);
     for (int a = 0; a < sh.rank; ++a)
       if (a != sh.phys_axis && sh.dims[a] > maxD) return false;
@@ -897,7 +903,10 @@ struct Builder {
     o.desc = t.heff_desc[u];  // shape
     o.axis = ax;
     o.p1 = t.T[u];
-    if ((size_t)rows * (cols + 2) <= (size_t)kQrLdsEntries) {
+    // one workgroup (LDS-resident, or streaming through L2 up to
+    // kQrOneGroupRows rows); taller matrices split rows over workgroups with
+    // one launch per phase and column
+    if ((size_t)rows * (cols + 2) <= (size_t)kQrLdsEntries || rows <= kQrOneGroupRows) {
       out.push_back(o);
       return;
     }
@@ -1256,6 +1265,7 @@ int prepare(ttns_ctx& c, std::vector<TreeState>&& trees, const ttns_opts* opts, 
   if (!(o.rank_tol > 0) || !(o.breakdown_tol > 0)) return fail(TTNS_EINVAL, "tolerances must be > 0");
   if (o.precision < TTNS_FP64 || o.precision > TTNS_BF16X3) return fail(TTNS_EINVAL, "bad precision");
   if (o.executor < TTNS_EXEC_AUTO || o.executor > TTNS_EXEC_PERSISTENT) return fail(TTNS_EINVAL, "bad executor");
+  if (o.flags & ~TTNS_FLAG_MFMA_ALL) return fail(TTNS_EINVAL, "unknown option flags");
   c.opts = o;
   c.trees = std::move(trees);
   c.persistent = (o.executor == TTNS_EXEC_PERSISTENT) ||
@@ -1563,25 +1573,41 @@ int validate_program(ttns_ctx& c, const std::vector<Op>& ops, bool allow_user_xy
   return TTNS_OK;
 }
 
-int build_graph(ttns_ctx& c) {
-  if (c.gexec) return TTNS_OK;
+int capture_segment(ttns_ctx& c, const Op* ops, size_t n) {
   HIPCHK(hipStreamBeginCapture(c.cap, hipStreamCaptureModeThreadLocal));
   hipError_t err = hipSuccess;
   if (c.persistent) {
     err = launch_persistent(c.d_ops, c.d_begin, c.d_end, (int)c.trees.size(), c.tables, c.cap);
   } else {
-    for (const Op& o : c.step_ops) {
-      err = launch_op(o, c.tables, c.cap);
-      if (err != hipSuccess) break;
-    }
+    for (size_t i = 0; i < n && err == hipSuccess; ++i) err = launch_op(ops[i], c.tables, c.cap);
   }
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(c.cap, &g);
+  if (g) c.graphs.push_back(g);
   if (err != hipSuccess) return fail(TTNS_EDEVICE, std::string("capture: ") + hipGetErrorString(err));
   if (e2 != hipSuccess) return fail(TTNS_EDEVICE, std::string("end capture: ") + hipGetErrorString(e2));
-  c.graph = g;
-  HIPCHK(hipGraphInstantiate(&c.gexec, g, nullptr, nullptr, 0));
+  hipGraphExec_t ge = nullptr;
+  HIPCHK(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+  c.gexecs.push_back(ge);
   return TTNS_OK;
+}
+
+int build_graph(ttns_ctx& c) {
+  if (!c.gexecs.empty()) return TTNS_OK;
+  int rc = TTNS_OK;
+  if (c.persistent) {
+    rc = capture_segment(c, nullptr, 0);
+  } else {
+    for (size_t i = 0; i < c.step_ops.size() && !rc; i += kGraphSegment)
+      rc = capture_segment(c, c.step_ops.data() + i, std::min(kGraphSegment, c.step_ops.size() - i));
+  }
+  if (rc) {
+    for (auto ge : c.gexecs) (void)hipGraphExecDestroy(ge);
+    for (auto g : c.graphs) (void)hipGraphDestroy(g);
+    c.gexecs.clear();
+    c.graphs.clear();
+  }
+  return rc;
 }
 
 int recentre(ttns_ctx& c) {
@@ -1621,6 +1647,10 @@ std::vector<TreeState> trees_from_star(const ttns_star_model* m, int n, std::str
 }
 
 }  // namespace
+
+namespace ttns {
+int set_error(int code, const std::string& msg) { return fail(code, msg); }
+}  // namespace ttns
 
 // ====================================================================== C-ABI
 extern "C" {
@@ -1742,7 +1772,8 @@ int ttns_tdvp_step(ttns_ctx* c, double dt, int32_t n_steps) {
     return TTNS_OK;
   }
   if ((rc = build_graph(*c))) return rc;
-  for (int s = 0; s < n_steps; ++s) HIPCHK(hipGraphLaunch(c->gexec, c->stream));
+  for (int s = 0; s < n_steps; ++s)
+    for (auto ge : c->gexecs) HIPCHK(hipGraphLaunch(ge, c->stream));
   return TTNS_OK;
 }
 
@@ -1869,8 +1900,8 @@ int ttns_profile_kernel(ttns_ctx* c, int32_t kernel, double* total_ms, int64_t* 
 int ttns_destroy(ttns_ctx* c) {
   if (!c) return TTNS_OK;
   drain_profile(*c);
-  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
-  if (c->graph) (void)hipGraphDestroy(c->graph);
+  for (auto ge : c->gexecs) (void)hipGraphExecDestroy(ge);
+  for (auto g : c->graphs) (void)hipGraphDestroy(g);
   if (c->cap) (void)hipStreamDestroy(c->cap);
   delete c;
   return TTNS_OK;

@@ -12,32 +12,13 @@
 // diagonal, then Re and Im of the upper triangle (j < k, row-major).
 #include <hip/hip_runtime.h>
 
-#include "ttns_internal.h"
+#include <algorithm>
+
+#include "learn_internal.h"
 
 namespace ttns {
 
 typedef float f4v __attribute__((ext_vector_type(4)));
-
-enum GemmEpi : int {
-  EPI_STORE = 0,     // C = A B
-  EPI_BIAS_TANH,     // C = tanh(A B + bias)
-  EPI_BIAS_RESID,    // C = A B + bias + R
-  EPI_TANH_BACK,     // C = (A B) * (1 - H^2)
-};
-
-struct GemmArgs {
-  int M, N, K;
-  const float* A;
-  int sam, sak;  // A[m][k] = A[m * sam + k * sak]
-  const float* B;
-  int sbk, sbn;  // B[k][n] = B[k * sbk + n * sbn]
-  float* C;
-  int ldc;       // C[m][n] = C[m * ldc + n]
-  int epi;
-  const float* bias;
-  const float* R;  // residual (EPI_BIAS_RESID) or H (EPI_TANH_BACK)
-  int ldr;
-};
 
 constexpr int GT = 64, GK = 16;
 
@@ -285,6 +266,50 @@ __global__ void k_judge(const float* dist, int B, int T, float tol, int* accept,
   accept[b] = mx <= tol ? 1 : 0;
 }
 
+// X[b] = [init[b] (window x ne), cond[b]]
+__global__ void k_rollout_init(const float* init, const float* cond, int ne, int window, int nc, float* X) {
+  const int b = blockIdx.x;
+  const int in = window * ne + nc;
+  for (int i = threadIdx.x; i < in; i += blockDim.x)
+    X[(size_t)b * in + i] = i < window * ne ? init[(size_t)b * window * ne + i] : cond[(size_t)b * nc + i - window * ne];
+}
+
+// rdm: count x n x n complex (re, im doubles, row-major) -> n^2 reals
+__global__ void k_encode(const double* rdm, long long count, int n, float* out) {
+  const int ne = n * n, m = n * (n - 1) / 2;
+  const long long total = count * ne;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long c = i / ne;
+    const int e = (int)(i % ne);
+    const double* r = rdm + (size_t)c * ne * 2;
+    double v;
+    if (e < n) {
+      v = r[2 * (e * n + e)];
+    } else {
+      const int q = e < n + m ? e - n : e - n - m;  // upper-triangle index
+      int j = 0, rem = q;
+      while (rem >= n - 1 - j) {
+        rem -= n - 1 - j;
+        ++j;
+      }
+      const int k = j + 1 + rem;
+      v = r[2 * (j * n + k) + (e < n + m ? 0 : 1)];
+    }
+    out[i] = (float)v;
+  }
+}
+
+// out[b] = accept[b] ? pred[b] : ref[b], `per` floats per b
+__global__ void k_select(const float* pred, const float* ref, const int* accept, int B, long long per, float* out) {
+  const long long total = (long long)B * per;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int b = (int)(i / per);
+    out[i] = accept[b] ? pred[i] : ref[i];
+  }
+}
+
 // ---------------------------------------------------------------- launchers
 hipError_t learn_gemm(const GemmArgs& g, hipStream_t s) {
   const dim3 grid((g.N + GT - 1) / GT, (g.M + GT - 1) / GT);
@@ -319,6 +344,24 @@ hipError_t learn_rollout_post(const float* P, float* X, int B, int ne, int n, in
 }
 hipError_t learn_trace_distance(const float* a, const float* b, int count, int n, float* dist, hipStream_t s) {
   hipLaunchKernelGGL(k_trace_distance, dim3((count + 127) / 128), dim3(128), 0, s, a, b, count, n, dist);
+  return hipGetLastError();
+}
+hipError_t learn_rollout_init(const float* init, const float* cond, int B, int ne, int window, int nc, float* X,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_rollout_init, dim3(B), dim3(256), 0, s, init, cond, ne, window, nc, X);
+  return hipGetLastError();
+}
+hipError_t learn_encode(const double* rdm, long long count, int n, float* out, hipStream_t s) {
+  const long long total = count * n * n;
+  const unsigned nb = (unsigned)std::min<long long>(4096, (total + 255) / 256);
+  hipLaunchKernelGGL(k_encode, dim3(nb), dim3(256), 0, s, rdm, count, n, out);
+  return hipGetLastError();
+}
+hipError_t learn_select(const float* pred, const float* ref, const int* accept, int B, long long per, float* out,
+                        hipStream_t s) {
+  const long long total = (long long)B * per;
+  const unsigned nb = (unsigned)std::min<long long>(4096, (total + 255) / 256);
+  hipLaunchKernelGGL(k_select, dim3(nb), dim3(256), 0, s, pred, ref, accept, B, per, out);
   return hipGetLastError();
 }
 hipError_t learn_judge(const float* dist, int B, int T, float tol, int* accept, float* worst, hipStream_t s) {

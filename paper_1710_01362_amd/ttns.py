@@ -22,6 +22,7 @@ TTNS_ENUMERIC = -4
 
 TTNS_FP64, TTNS_FP32, TTNS_BF16X3 = 0, 1, 2
 TTNS_EXEC_AUTO, TTNS_EXEC_WIDE, TTNS_EXEC_PERSISTENT = 0, 1, 2
+TTNS_FLAG_MFMA_ALL = 1
 
 OBS_RDM, OBS_POP, OBS_LOCAL, OBS_NORM, OBS_ENERGY = 0, 1, 2, 3, 4
 OBS_HISTORY, OBS_RECORD_SIZE, OBS_TENSOR, OBS_STATS, OBS_BOND_DIMS = 5, 6, 7, 8, 9

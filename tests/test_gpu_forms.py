@@ -7,6 +7,8 @@
   the dropped lo*lo term is ~2^-32) and products are accumulated in FP32
   over K = 2D terms, so the elementwise error is bounded by ~K * 2^-24 of the
   row norm; we hold it to 2e-5 relative to the largest entry.
+  (Small trees: every node is put on the matrix cores with
+  TTNS_FLAG_MFMA_ALL; by default only nodes of >= 16384 entries are.)
 * Whole trajectories with the reduced-precision contractions (Lanczos,
   exponentials, QR and environments stay FP64): population error against the
   FP64 oracle within 1e-5 (stated tolerance of the precision forms).
@@ -30,7 +32,8 @@ def _apply_vs_oracle(m, precision, nodes, rel):
     import torch
     T = _T()
     ctx = T.Context([m], opts=T.default_opts(record_capacity=2, precision=precision,
-                                             executor=T.TTNS_EXEC_WIDE))
+                                             executor=T.TTNS_EXEC_WIDE,
+                                             flags=T.TTNS_FLAG_MFMA_ALL))
     tt = TTNS(build_tree(m))
     rng = np.random.default_rng(11)
     worst = 0.0
@@ -69,7 +72,8 @@ def test_reduced_precision_apply(precision, topology):
 def test_reduced_precision_trajectory_population_error(precision):
     T = _T()
     m = W.vibronic(seed=2, n_chains=4, L=8, d=8, D=8, steps=20)
-    ctx = T.Context([m], opts=T.default_opts(record_capacity=m["steps"] + 1, precision=precision))
+    ctx = T.Context([m], opts=T.default_opts(record_capacity=m["steps"] + 1, precision=precision,
+                                             flags=T.TTNS_FLAG_MFMA_ALL))
     ctx.ttns_tdvp_step(m["dt"], m["steps"])
     hg = ctx.history()
     ctx.close()
