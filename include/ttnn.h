@@ -100,8 +100,12 @@ int ttnn_gradients(ttnn_net* net, const int32_t* host_samples, int32_t batch, fl
                    float* host_grad);
 
 /* One Adam step on one batch (same samples as ttnn_gradients) with
- * learning rate lr.  Asynchronous; ttnn_last_loss reads its loss. */
-int ttnn_train_step(ttnn_net* net, const int32_t* host_samples, int32_t batch, float lr);
+ * learning rate lr.  dev_noise (device, batch x window n^2 floats, or NULL)
+ * is added to the input RDM window of each sample (not to the target): the
+ * caller draws it, e.g. Gaussian, to train a map that pulls perturbed
+ * histories back towards the data, which keeps long rollouts stable.
+ * Asynchronous; ttnn_last_loss reads its loss. */
+int ttnn_train_step(ttnn_net* net, const int32_t* host_samples, int32_t batch, float lr, const float* dev_noise);
 
 /* Loss of the last ttnn_train_step or ttnn_gradients call.  Synchronous. */
 int ttnn_last_loss(ttnn_net* net, float* host_loss);

@@ -756,6 +756,7 @@ struct Builder {
       o.i0 = m.prec;
       o.n = m.n_rest;
       o.axis = m.sh.dims[m.sh.phys_axis];
+      o.j = mode_padded(m.prec, m.sh.dims[m.axis]);
       out.push_back(o);
     }
     for (int id : t.mode_groups[v]) {
@@ -768,6 +769,7 @@ struct Builder {
       o.i0 = m.prec;
       o.n = m.n_rest;
       o.axis = m.sh.dims[m.sh.phys_axis];
+      o.j = mode_padded(m.prec, m.sh.dims[m.axis]);
       out.push_back(o);
     }
   }
@@ -1529,7 +1531,8 @@ int validate_program(ttns_ctx& c, const std::vector<Op>& ops, bool allow_user_xy
           if (m.op[e]) rc.in(m.op[e], (size_t)dp * dp * C, "entry operator");
         }
         if (m.axis == m.sh.phys_axis || D > mode_max_bond(m.prec) || o.n != m.n_rest ||
-            o.axis != dp || o.i0 != m.prec || m.n_e < 1 || m.n_e > kMaxGroup)
+            o.axis != dp || o.i0 != m.prec || m.n_e < 1 || m.n_e > kMaxGroup ||
+            o.j != mode_padded(m.prec, D))
           rc.err = "internal: matrix-core group";
         break;
       }

@@ -89,9 +89,10 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
       }
 }
 
-// X[b] = [traj[s][t-window+1 .. t] (window x ne), cond[s]], Y[b] = traj[s][t+1]
+// X[b] = [traj[s][t-window+1 .. t] (window x ne) (+ noise[b]), cond[s]],
+// Y[b] = traj[s][t+1]
 __global__ void k_windows(const int* samples, const float* traj, int T, const float* cond, int ne,
-                          int window, int nc, float* X, float* Y, int B) {
+                          int window, int nc, float* X, float* Y, int B, const float* noise) {
   const int b = blockIdx.x;
   if (b >= B) return;
   const int s = samples[2 * b], t = samples[2 * b + 1];
@@ -99,8 +100,12 @@ __global__ void k_windows(const int* samples, const float* traj, int T, const fl
   const float* tr = traj + (size_t)s * T * ne;
   for (int i = threadIdx.x; i < in; i += blockDim.x) {
     float v;
-    if (i < window * ne) v = tr[(size_t)(t - window + 1) * ne + i];
-    else v = cond[(size_t)s * nc + (i - window * ne)];
+    if (i < window * ne) {
+      v = tr[(size_t)(t - window + 1) * ne + i];
+      if (noise) v += noise[(size_t)b * window * ne + i];
+    } else {
+      v = cond[(size_t)s * nc + (i - window * ne)];
+    }
     X[(size_t)b * in + i] = v;
   }
   if (Y)
@@ -317,8 +322,8 @@ hipError_t learn_gemm(const GemmArgs& g, hipStream_t s) {
   return hipGetLastError();
 }
 hipError_t learn_windows(const int* samples, const float* traj, int T, const float* cond, int ne,
-                         int window, int nc, float* X, float* Y, int B, hipStream_t s) {
-  hipLaunchKernelGGL(k_windows, dim3(B), dim3(256), 0, s, samples, traj, T, cond, ne, window, nc, X, Y, B);
+                         int window, int nc, float* X, float* Y, int B, const float* noise, hipStream_t s) {
+  hipLaunchKernelGGL(k_windows, dim3(B), dim3(256), 0, s, samples, traj, T, cond, ne, window, nc, X, Y, B, noise);
   return hipGetLastError();
 }
 hipError_t learn_loss(const float* P, const float* Y, int n, float* G, float* partial, int nb, float* loss,

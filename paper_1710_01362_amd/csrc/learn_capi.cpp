@@ -186,7 +186,7 @@ int backward(ttnn_net& n, int B) {
   return TTNS_OK;
 }
 
-int load_batch(ttnn_net& n, const int32_t* host_samples, int batch) {
+int load_batch(ttnn_net& n, const int32_t* host_samples, int batch, const float* dev_noise = nullptr) {
   if (!n.traj) return set_error(TTNS_EINVAL, "ttnn: no training data (ttnn_set_data)");
   if (!host_samples || batch < 1 || batch > n.cfg.max_batch)
     return set_error(TTNS_EINVAL, "ttnn: batch must be in [1, max_batch]");
@@ -198,7 +198,7 @@ int load_batch(ttnn_net& n, const int32_t* host_samples, int batch) {
   LCHK(hipMemcpyAsync(n.samples, host_samples, (size_t)batch * 2 * sizeof(int32_t), hipMemcpyHostToDevice,
                       n.stream));
   LCHK(learn_windows(n.samples, n.traj, n.n_times, n.cond, n.ne, n.cfg.window, n.cfg.n_cond, n.X, n.Y, batch,
-                     n.stream));
+                     dev_noise, n.stream));
   return TTNS_OK;
 }
 
@@ -292,9 +292,9 @@ int ttnn_gradients(ttnn_net* n, const int32_t* host_samples, int32_t batch, floa
   return TTNS_OK;
 }
 
-int ttnn_train_step(ttnn_net* n, const int32_t* host_samples, int32_t batch, float lr) {
+int ttnn_train_step(ttnn_net* n, const int32_t* host_samples, int32_t batch, float lr, const float* dev_noise) {
   if (!n || !(lr > 0)) return set_error(TTNS_EINVAL, "ttnn_train_step: bad arguments");
-  int rc = load_batch(*n, host_samples, batch);
+  int rc = load_batch(*n, host_samples, batch, dev_noise);
   if (!rc) rc = forward(*n, batch);
   if (!rc) rc = backward(*n, batch);
   if (rc) return rc;

@@ -31,7 +31,7 @@ struct GemmArgs {
 
 hipError_t learn_gemm(const GemmArgs& g, hipStream_t s);
 hipError_t learn_windows(const int* samples, const float* traj, int T, const float* cond, int ne, int window,
-                         int nc, float* X, float* Y, int B, hipStream_t s);
+                         int nc, float* X, float* Y, int B, const float* noise, hipStream_t s);
 hipError_t learn_loss(const float* P, const float* Y, int n, float* G, float* partial, int nb, float* loss,
                       hipStream_t s);
 hipError_t learn_colsum(const float* G, int M, int N, float* db, hipStream_t s);

@@ -2,21 +2,26 @@
 //
 // One launch handles one ModeDesc group (all terms of an H_eff apply that
 // act on one bond axis with one source tensor):
-//   y[s] (+)= sum_o M_{s,o} x_axis src[s + o],   M_{s,o} = sum_e coef_e g_e(s,o) E_e.
-// Workgroup (blockIdx.y = output physical index s, blockIdx.x = tile of
-// kModeNT "rest" columns, i.e. all indices other than the bond axis and the
-// physical leg).  For every band offset o the workgroup builds the real form
-//   A = [[Re M, -Im M], [Im M, Re M]]   (2D x 2D, zero-padded to DP)
-// and B = [Re src; Im src] (2D x kModeNT) in LDS, and accumulates
-// Y = A B on 16x16 MFMA tiles: wavefront w owns output columns 16w..16w+15
-// and every row block.  Precisions:
+//   y[s] (+)= sum_e E_e x_axis Z_{e,s},   Z_{e,s} = sum_o coef_e g_e(s,o) src[s + o],
+// with g_e(s,o) = op_e[s][s + o] (the identity when the term has no local
+// operator).  Workgroup (blockIdx.y = output physical index s, blockIdx.x =
+// tile of kModeNT "rest" columns, i.e. all indices other than the bond axis
+// and the physical leg).  For every term e the workgroup stages the real form
+//   A_e = [[Re E_e, -Im E_e], [Im E_e, Re E_e]]   (2D x 2D, zero-padded to DP)
+// and B_e = [Re Z_{e,s}; Im Z_{e,s}] (2D x kModeNT) in LDS and accumulates
+// Y += A_e B_e on 16x16 MFMA tiles: wavefront w owns output columns
+// 16w..16w+15 and every row block.  A_e does not depend on s and B_e needs
+// only the band of g_e, so every global load is a plain independent load of
+// an environment matrix or a source slice, issued in batches.
+// Operand layouts (all precisions): lane l supplies A[l % 16][k-group l / 16]
+// and B[k-group l / 16][l % 16]; the accumulator layouts differ (epilogue).
 //   FP64  : v_mfma_f64_16x16x4 (A, B and accumulation in FP64)
-// Operand layouts (all three): lane l supplies A[l % 16][k-group l / 16] and
-// B[k-group l / 16][l % 16]; the accumulator layouts differ (see epilogue).
 //   FP32  : v_mfma_f32_16x16x4 (A, B rounded to FP32, FP32 accumulation)
 //   BF16X3: v_mfma_f32_16x16x32_bf16 three times per step, x = hi + lo with
 //           hi = bf16(x), lo = bf16(x - hi): hi*hi + hi*lo + lo*hi, FP32
 //           accumulation.
+// Two tile sizes per precision: DP up to 48 (FP64) / 64 (others), whose LDS
+// footprint lets several workgroups share a compute unit, and the full one.
 // The epilogue stages Y through LDS, pairs real and imaginary rows and
 // writes (or adds to) the FP64 output, adding the on-site term in FP64 for
 // the first group of an apply.
@@ -32,6 +37,10 @@ typedef double d4v __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 
 int mode_max_bond(int prec) { return prec == TTNS_FP64 ? 48 : 64; }
+int mode_padded(int prec, int D) {
+  const int pad = prec == TTNS_BF16X3 ? 32 : 16;
+  return (2 * D + pad - 1) / pad * pad;
+}
 
 namespace {
 
@@ -46,14 +55,6 @@ __device__ __forceinline__ unsigned short bf16_bits(float x) {
 }
 __device__ __forceinline__ float bf16_float(unsigned short b) { return __uint_as_float(((unsigned int)b) << 16); }
 
-// g_e(s, o): weight of term e for output index s reading input index s + o
-__device__ __forceinline__ cd term_weight(const ModeDesc& m, int e, int s, int o, int d) {
-  if (!m.op[e]) return o == 0 ? make_double2(m.coef[e], 0.0) : cz();
-  if (o < m.lo[e] || o > m.hi[e] || s + o < 0 || s + o >= d) return cz();
-  const cd g = m.op[e][s * d + s + o];
-  return make_double2(m.coef[e] * g.x, m.coef[e] * g.y);
-}
-
 // rest column r -> tensor offset (all axes but the bond axis and the phys leg)
 __device__ __forceinline__ int rest_offset(const Shape& sh, int ax, int r) {
   int off = 0;
@@ -66,35 +67,62 @@ __device__ __forceinline__ int rest_offset(const Shape& sh, int ax, int r) {
 }
 
 template <int PREC>
-struct Tile;
-
-// FP64 / FP32: A row-major [DP][DP + 1], B column-major [NT][DP + 1]
+struct Prec;
 template <>
-struct Tile<TTNS_FP64> {
+struct Prec<TTNS_FP64> {
   using T = double;
-  static constexpr int DPMAX = 96, KS = 4, KPAD = 16;
+  static constexpr int KS = 4, KPAD = 16, SMALL = 48, BIG = 96;
 };
 template <>
-struct Tile<TTNS_FP32> {
+struct Prec<TTNS_FP32> {
   using T = float;
-  static constexpr int DPMAX = 128, KS = 4, KPAD = 16;
+  static constexpr int KS = 4, KPAD = 16, SMALL = 64, BIG = 128;
 };
 template <>
-struct Tile<TTNS_BF16X3> {
+struct Prec<TTNS_BF16X3> {
   using T = unsigned short;  // bf16 bits, hi and lo planes
-  static constexpr int DPMAX = 128, KS = 32, KPAD = 32;
+  static constexpr int KS = 32, KPAD = 32, SMALL = 64, BIG = 128;
 };
 
+// store v (FP64) into plane 0 (and the bf16 remainder into plane 1)
 template <int PREC>
+__device__ __forceinline__ void put(typename Prec<PREC>::T* p0, typename Prec<PREC>::T* p1, int idx, double v) {
+  if constexpr (PREC == TTNS_BF16X3) {
+    const unsigned short hi = bf16_bits((float)v);
+    p0[idx] = hi;
+    p1[idx] = bf16_bits((float)(v - (double)bf16_float(hi)));
+  } else {
+    (void)p1;
+    p0[idx] = (typename Prec<PREC>::T)v;
+  }
+}
+
+template <int PREC, int DPMAX>
+struct ModeSmem {
+  using T = typename Prec<PREC>::T;
+  static constexpr bool kSplit = PREC == TTNS_BF16X3;
+  static constexpr int LDA = DPMAX + (kSplit ? 8 : 1);  // row stride of A and column stride of B
+  static constexpr int PLANES = kSplit ? 2 : 1;
+  static constexpr size_t kA = (size_t)PLANES * DPMAX * LDA * sizeof(T);
+  static constexpr size_t kB = (size_t)PLANES * NT * LDA * sizeof(T);
+  static constexpr size_t kY = (size_t)DPMAX * NT * sizeof(double);
+  static constexpr size_t kBytes = (kA + kB > kY ? kA + kB : kY);
+};
+
+template <int PREC, int DPMAX>
 __global__ __launch_bounds__(kBlock) void k_mode(Op op, DevTables Tb) {
-  using C = Tile<PREC>;
-  using T = typename C::T;
-  constexpr bool kSplit = PREC == TTNS_BF16X3;
-  constexpr int LDA = C::DPMAX + (kSplit ? 8 : 1);  // row stride (elements) of A and B
-  constexpr int PLANES = kSplit ? 2 : 1;
-  __shared__ T As[PLANES][C::DPMAX * LDA];
-  __shared__ T Bs[PLANES][NT * LDA];
+  using P = Prec<PREC>;
+  using S = ModeSmem<PREC, DPMAX>;
+  using T = typename P::T;
+  constexpr bool kSplit = S::kSplit;
+  constexpr int LDA = S::LDA;
+  // A planes, then B planes; the epilogue reuses the space for Y (doubles)
+  __shared__ __align__(16) unsigned char smem[S::kBytes];
   __shared__ int roff[NT];
+  T* A0 = reinterpret_cast<T*>(smem);
+  T* A1 = A0 + DPMAX * LDA;
+  T* B0 = reinterpret_cast<T*>(smem + S::kA);
+  T* B1 = B0 + NT * LDA;
 
   const ModeDesc& m = Tb.modes[op.desc];
   const Shape& sh = m.sh;
@@ -102,104 +130,141 @@ __global__ __launch_bounds__(kBlock) void k_mode(Op op, DevTables Tb) {
   const int D = sh.dims[ax], d = sh.dims[pa];
   const int sa = sh.stride[ax], sp = sh.stride[pa];
   const int D2 = 2 * D;
-  const int DP = (D2 + C::KPAD - 1) / C::KPAD * C::KPAD;
+  const int DP = (D2 + P::KPAD - 1) / P::KPAD * P::KPAD;
   const int s = blockIdx.y;
   const int r0 = blockIdx.x * NT;
   const int ncol = min(NT, m.n_rest - r0);
   const cd* src = op.p0 ? op.p0 : m.src;
   cd* y = op.p1 ? op.p1 : m.y;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const bool bfast = sa == 1;  // bond index fastest in memory
 
   for (int c = t; c < NT; c += kBlock) roff[c] = c < ncol ? rest_offset(sh, ax, r0 + c) : 0;
+  // zero padding: A rows and columns >= 2D, B rows >= 2D (never rewritten)
+  for (int i = t; i < DP * DP; i += kBlock) {
+    const int row = i / DP, col = i % DP;
+    if (row >= D2 || col >= D2) put<PREC>(A0, A1, row * LDA + col, 0.0);
+  }
+  for (int i = t; i < NT * (DP - D2); i += kBlock) {
+    const int c = i / (DP - D2), k = D2 + i % (DP - D2);
+    put<PREC>(B0, B1, c * LDA + k, 0.0);
+  }
 
   using Acc = typename std::conditional<PREC == TTNS_FP64, d4v, f4v>::type;
-  Acc acc[C::DPMAX / 16];
+  Acc acc[DPMAX / 16];
 #pragma unroll
-  for (int i = 0; i < C::DPMAX / 16; ++i) acc[i] = Acc{0, 0, 0, 0};
+  for (int i = 0; i < DPMAX / 16; ++i) acc[i] = Acc{0, 0, 0, 0};
 
-  for (int o = m.band_lo; o <= m.band_hi; ++o) {
-    const int si = s + o;
-    if (si < 0 || si >= d) continue;
+  constexpr int kU = (DPMAX / 2) * NT / kBlock;  // B elements (complex) per thread, D <= DPMAX / 2
+  constexpr int kUA = (DPMAX / 2) * (DPMAX / 2) / kBlock + 1;
+  const int nz = D * NT;  // complex B elements
+  for (int e = 0; e < m.n_e; ++e) {
+    const cd* op_e = m.op[e];
+    const double coef = m.coef[e];
+    const int olo = op_e ? max(m.lo[e], -s) : 0;
+    const int ohi = op_e ? min(m.hi[e], d - 1 - s) : 0;
     bool any = false;
-    for (int e = 0; e < m.n_e; ++e) {
-      const cd g = term_weight(m, e, s, o, d);
+    for (int o = olo; o <= ohi; ++o) {
+      const cd g = op_e ? op_e[s * d + s + o] : make_double2(1.0, 0.0);
       any = any || g.x != 0.0 || g.y != 0.0;
     }
-    if (!any) continue;
-    __syncthreads();  // previous offset's operands are consumed
-    // A = real form of M_{s,o}, zero padded to DP x DP
-    for (int i = t; i < DP * DP; i += kBlock) {
-      const int row = i / DP, col = i % DP;
-      double v = 0.0;
-      if (row < D2 && col < D2) {
-        const int a = row % D, b = col % D;
-        cd mm = cz();
-        for (int e = 0; e < m.n_e; ++e) mm = cfma(term_weight(m, e, s, o, d), m.E[e][a * D + b], mm);
-        const bool rr = row < D, cr = col < D;
-        v = (rr == cr) ? mm.x : (rr ? -mm.y : mm.y);
+    if (!any) continue;  // uniform: every thread read the same weights
+    __syncthreads();  // the previous term's operands are consumed
+    // A_e: real form of E_e, loads batched per thread
+    const cd* E = m.E[e];
+    {
+      cd v[kUA];
+#pragma unroll
+      for (int u = 0; u < kUA; ++u) {
+        const int i = t + u * kBlock;
+        v[u] = i < D * D ? E[i] : cz();
       }
-      if constexpr (kSplit) {
-        const unsigned short hi = bf16_bits((float)v);
-        As[0][row * LDA + col] = hi;
-        As[1][row * LDA + col] = bf16_bits((float)(v - (double)bf16_float(hi)));
-      } else {
-        As[0][row * LDA + col] = (T)v;
+#pragma unroll
+      for (int u = 0; u < kUA; ++u) {
+        const int i = t + u * kBlock;
+        if (i < D * D) {
+          const int a = i / D, b = i % D;
+          put<PREC>(A0, A1, a * LDA + b, v[u].x);
+          put<PREC>(A0, A1, a * LDA + D + b, -v[u].y);
+          put<PREC>(A0, A1, (D + a) * LDA + b, v[u].y);
+          put<PREC>(A0, A1, (D + a) * LDA + D + b, v[u].x);
+        }
       }
     }
-    // B (column-major: Bs[col][k]) = [Re src; Im src] at physical index si
-    const bool bfast = sa == 1;
-    for (int i = t; i < DP * NT; i += kBlock) {
-      int k, c;
-      if (bfast) {
-        k = i % DP;
-        c = i / DP;
-      } else {
-        c = i % NT;
-        k = i / NT;
+    // B_e = Z_{e,s}: band-weighted source slices, accumulated in registers
+    {
+      cd z[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) z[u] = cz();
+      for (int o = olo; o <= ohi; ++o) {
+        const cd g = op_e ? op_e[s * d + s + o] : make_double2(1.0, 0.0);
+        if (g.x == 0.0 && g.y == 0.0) continue;
+        const cd wgt = make_double2(coef * g.x, coef * g.y);
+        const cd* base = src + (size_t)(s + o) * sp;
+        cd v[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int i = t + u * kBlock;
+          int b, c;
+          if (bfast) {
+            b = i % D;
+            c = i / D;
+          } else {
+            c = i % NT;
+            b = i / NT;
+          }
+          v[u] = (i < nz && c < ncol) ? base[b * sa + roff[c]] : cz();
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) z[u] = cfma(wgt, v[u], z[u]);
       }
-      double v = 0.0;
-      if (k < D2 && c < ncol) {
-        const cd xv = src[si * sp + (k % D) * sa + roff[c]];
-        v = k < D ? xv.x : xv.y;
-      }
-      if constexpr (kSplit) {
-        const unsigned short hi = bf16_bits((float)v);
-        Bs[0][c * LDA + k] = hi;
-        Bs[1][c * LDA + k] = bf16_bits((float)(v - (double)bf16_float(hi)));
-      } else {
-        Bs[0][c * LDA + k] = (T)v;
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int i = t + u * kBlock;
+        if (i < nz) {
+          int b, c;
+          if (bfast) {
+            b = i % D;
+            c = i / D;
+          } else {
+            c = i % NT;
+            b = i / NT;
+          }
+          put<PREC>(B0, B1, c * LDA + b, z[u].x);
+          put<PREC>(B0, B1, c * LDA + D + b, z[u].y);
+        }
       }
     }
     __syncthreads();
     const int col = w * 16 + (lane & 15);
     const int kq = lane >> 4;
-    for (int kk = 0; kk < DP; kk += C::KS) {
+    for (int kk = 0; kk < DP; kk += P::KS) {
       if constexpr (kSplit) {
         const int k0 = kk + 8 * kq;
         bf8v bh, bl;
         for (int q = 0; q < 8; ++q) {
-          bh[q] = __builtin_bit_cast(__bf16, Bs[0][col * LDA + k0 + q]);
-          bl[q] = __builtin_bit_cast(__bf16, Bs[1][col * LDA + k0 + q]);
+          bh[q] = __builtin_bit_cast(__bf16, B0[col * LDA + k0 + q]);
+          bl[q] = __builtin_bit_cast(__bf16, B1[col * LDA + k0 + q]);
         }
 #pragma unroll
-        for (int bi = 0; bi < C::DPMAX / 16; ++bi) {
+        for (int bi = 0; bi < DPMAX / 16; ++bi) {
           if (bi * 16 >= DP) break;
           const int row = bi * 16 + (lane & 15);
           bf8v ah, al;
           for (int q = 0; q < 8; ++q) {
-            ah[q] = __builtin_bit_cast(__bf16, As[0][row * LDA + k0 + q]);
-            al[q] = __builtin_bit_cast(__bf16, As[1][row * LDA + k0 + q]);
+            ah[q] = __builtin_bit_cast(__bf16, A0[row * LDA + k0 + q]);
+            al[q] = __builtin_bit_cast(__bf16, A1[row * LDA + k0 + q]);
           }
           acc[bi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[bi], 0, 0, 0);
           acc[bi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[bi], 0, 0, 0);
           acc[bi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[bi], 0, 0, 0);
         }
       } else {
-        const T bv = Bs[0][col * LDA + kk + kq];
+        const T bv = B0[col * LDA + kk + kq];
 #pragma unroll
-        for (int bi = 0; bi < C::DPMAX / 16; ++bi) {
+        for (int bi = 0; bi < DPMAX / 16; ++bi) {
           if (bi * 16 >= DP) break;
-          const T av = As[0][(bi * 16 + (lane & 15)) * LDA + kk + kq];
+          const T av = A0[(bi * 16 + (lane & 15)) * LDA + kk + kq];
           if constexpr (PREC == TTNS_FP64)
             acc[bi] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[bi], 0, 0, 0);
           else
@@ -211,11 +276,11 @@ __global__ __launch_bounds__(kBlock) void k_mode(Op op, DevTables Tb) {
   __syncthreads();
   // epilogue: accumulators -> LDS (row-major Y[row][col] in double), then
   // pair real and imaginary rows
-  double* Ys = reinterpret_cast<double*>(&As[0][0]);  // DP x NT doubles fit in A
+  double* Ys = reinterpret_cast<double*>(smem);
   {
     const int col = w * 16 + (lane & 15);
 #pragma unroll
-    for (int bi = 0; bi < C::DPMAX / 16; ++bi) {
+    for (int bi = 0; bi < DPMAX / 16; ++bi) {
       if (bi * 16 >= DP) break;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -245,24 +310,30 @@ __global__ __launch_bounds__(kBlock) void k_mode(Op op, DevTables Tb) {
   }
 }
 
+template <int PREC>
+hipError_t launch_prec(const Op& op, const DevTables& t, hipStream_t s, dim3 grid) {
+  // op.j: padded real operand size DP of this group
+  if (op.j <= Prec<PREC>::SMALL)
+    hipLaunchKernelGGL((k_mode<PREC, Prec<PREC>::SMALL>), grid, dim3(kBlock), 0, s, op, t);
+  else
+    hipLaunchKernelGGL((k_mode<PREC, Prec<PREC>::BIG>), grid, dim3(kBlock), 0, s, op, t);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_mode(const Op& op, const DevTables& t, hipStream_t s, int prec, int n_rest, int d) {
-  const dim3 grid((n_rest + NT - 1) / NT, d), block(kBlock);
+  const dim3 grid((n_rest + NT - 1) / NT, d);
   switch (prec) {
     case TTNS_FP64:
-      hipLaunchKernelGGL(k_mode<TTNS_FP64>, grid, block, 0, s, op, t);
-      break;
+      return launch_prec<TTNS_FP64>(op, t, s, grid);
     case TTNS_FP32:
-      hipLaunchKernelGGL(k_mode<TTNS_FP32>, grid, block, 0, s, op, t);
-      break;
+      return launch_prec<TTNS_FP32>(op, t, s, grid);
     case TTNS_BF16X3:
-      hipLaunchKernelGGL(k_mode<TTNS_BF16X3>, grid, block, 0, s, op, t);
-      break;
+      return launch_prec<TTNS_BF16X3>(op, t, s, grid);
     default:
       return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 }  // namespace ttns

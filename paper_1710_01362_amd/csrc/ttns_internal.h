@@ -1,5 +1,5 @@
-// Internal types shared by the host planner (plan.cpp, capi.cpp) and the
-// device code (kernels.hip).  Plain structs of device pointers and sizes; the
+// Internal types shared by the host planner (capi.cpp, model.cpp) and the
+// device code (kernels.hip, mode_mfma.hip).  Plain structs of device pointers and sizes; the
 // host builds tables of them once per context and the kernels read them.
 #pragma once
 
@@ -63,12 +63,12 @@ struct ApplyDesc {
 };
 
 // One group of an H_eff apply on the matrix cores: every term acting on
-// bond axis `axis` with the same source tensor, as banded mode products
-//   y[s] (+)= sum_{o = band_lo..band_hi} M_{s,o} x_axis src[s + o],
-//   M_{s,o} = sum_e coef_e g_e(s, o) E_e,  g_e = op_e[s][s+o] (or delta_{o0}),
-// with the complex products done as real GEMMs [[Re M, -Im M], [Im M, Re M]]
-// . [Re src; Im src] on MFMA tiles (FP64, FP32 or split BF16).  The first
-// group of an apply writes y (plus the on-site term), later ones add.
+// bond axis `axis` with the same source tensor,
+//   y[s] (+)= sum_e E_e x_axis Z_{e,s},  Z_{e,s} = sum_o coef_e g_e(s, o) src[s + o],
+// g_e(s, o) = op_e[s][s+o] (or delta_{o0}) over the band [lo_e, hi_e], with
+// the complex products done as real GEMMs [[Re E, -Im E], [Im E, Re E]]
+// . [Re Z; Im Z] on MFMA tiles (FP64, FP32 or split BF16).  The first group
+// of an apply writes y (plus the on-site term), later ones add.
 constexpr int kMaxGroup = 8;
 struct ModeDesc {
   Shape sh;
@@ -229,5 +229,7 @@ hipError_t launch_set_half_step(double* dst, double h, hipStream_t s);
 // MFMA limits: bond dimension per precision, columns per workgroup tile
 constexpr int kModeNT = 64;
 int mode_max_bond(int prec);
+// padded real operand size (2D rounded up to the MFMA K granule) of a group
+int mode_padded(int prec, int D);
 
 }  // namespace ttns

@@ -39,7 +39,7 @@ def lib():
         L.ttnn_encode.argtypes = [P, P, C.c_int64, P]
         L.ttnn_set_data.argtypes = [P, P, P, I, I]
         L.ttnn_gradients.argtypes = [P, P, I, P, P]
-        L.ttnn_train_step.argtypes = [P, P, I, F]
+        L.ttnn_train_step.argtypes = [P, P, I, F, P]
         L.ttnn_last_loss.argtypes = [P, P]
         L.ttnn_get_params.argtypes = [P, P]
         L.ttnn_set_params.argtypes = [P, P]
@@ -139,9 +139,18 @@ class Net:
                                      grad.ctypes.data))
         return float(loss[0]), grad
 
-    def ttnn_train_step(self, samples, lr):
+    def ttnn_train_step(self, samples, lr, noise_dev=None):
+        """noise_dev: optional (B, window * n^2) float32 device tensor added to
+        the input windows."""
         samples = np.ascontiguousarray(samples, dtype=np.int32)
-        T.check(lib().ttnn_train_step(self.net, samples.ctypes.data, samples.shape[0], C.c_float(lr)))
+        nz = None
+        if noise_dev is not None:
+            nz = noise_dev.contiguous()
+            if nz.numel() != samples.shape[0] * self.cfg.window * self.cfg.n_levels ** 2:
+                raise ValueError("noise must hold batch x window x n^2 floats")
+            self._noise = nz
+        T.check(lib().ttnn_train_step(self.net, samples.ctypes.data, samples.shape[0], C.c_float(lr),
+                                      _ptr(nz) if nz is not None else None))
 
     def ttnn_last_loss(self):
         loss = np.zeros(1, dtype=np.float32)
