@@ -103,6 +103,8 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the H_eff and QR variants at build and plan the fastest")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the TDVP sweep of one tree is sequential and this "
@@ -116,8 +118,12 @@ def main():
     models = make()
     upd_per_step = sum(2 * W.node_count(m) for m in models)
     total = args.warmup + args.steps + args.profile_steps + 1
+    flags = T.TTNS_FLAG_AUTOTUNE if args.autotune else 0
+    t_build = time.perf_counter()
     ctx = T.Context(models, opts=T.default_opts(record_capacity=total + 1,
-                                                precision=PREC[args.precision]))
+                                                precision=PREC[args.precision], flags=flags))
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t_build
     dt = models[0]["dt"]
     persistent = len(models) > 1
 
@@ -146,7 +152,8 @@ def main():
         "config": {"workload": desc, "trees": len(models), "site_updates_per_step": upd_per_step,
                    "krylov": models[0]["krylov"],
                    "executor": "one persistent workgroup per tree" if persistent
-                   else "one kernel per operation, replayed as a HIP graph"},
+                   else "one kernel per operation, replayed as a HIP graph",
+                   "autotuned": bool(args.autotune), "build_s": round(t_build, 2)},
         "step_tflops": step_flops / (el / args.steps) / 1e12,
     }
     if persistent:
@@ -172,6 +179,8 @@ def main():
             out["heff_rooflines"].append(r)
         out["kernel_time_share"] = {kern[k]["name"]: round(kern[k]["ms"] / tot, 4)
                                     for k in sorted(kern, key=lambda k: -kern[k]["ms"])}
+    if args.autotune:
+        out["tuning"] = [l for l in ctx.tuning_report().splitlines() if l]
     torch.cuda.synchronize()
     h = ctx.history(0)
     out["drift"] = {"norm": float(np.abs(h["norm"] - 1).max()),

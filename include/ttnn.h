@@ -20,13 +20,20 @@
  * Network (FP32 storage, FP32 matrix-core products with FP32 accumulation):
  *   x   = [enc(rho_{t-window+1}), ..., enc(rho_t), cond]      (window n^2 + n_cond)
  *   h_1 = tanh(W_1 x + b_1), ..., h_L = tanh(W_L h_{L-1} + b_L)  (L = layers, width hidden)
- *   enc(rho_{t+1}) = enc(rho_t) + W_{L+1} h_L + b_{L+1}           (residual output)
+ *   enc(rho_{t+1}) = enc(U rho_t U^dagger) + W_{L+1} h_L + b_{L+1} (residual output)
+ * with U = exp(-i H_S dt) the free propagator of the electronic system
+ * Hamiltonian of Eq. (2) (or the identity when none is given): the network
+ * learns what the environment adds to the known system dynamics, as a
+ * transfer-tensor scheme learns a memory kernel on top of free evolution.
+ * With skip = 1 the input also carries cond_c * enc(rho_t)_e for every
+ * (c, e) (row-major), and the output adds W_s x (no bias): a linear,
+ * parameter-dependent transfer term with the MLP on top.
  * Loss: mean squared error over the batch and the n^2 outputs.  Optimiser:
  * Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected).
- * Rollout: predict, divide by the trace, append, shift the window.
+ * Rollout: propagate, predict, divide by the trace, append, shift the window.
  *
  * Parameter layout ("flat"): for each layer in order, W (out x in,
- * row-major) then b (out).
+ * row-major) then b (out); with the skip, W_s (n^2 x input, row-major) last.
  *
  * Conventions shared with ttns.h: calls return TTNS_OK or a negative
  * TTNS_E* code and never abort; ttns_last_error() gives the calling thread's
@@ -57,6 +64,7 @@ typedef struct {
   int32_t hidden;    /* width of every hidden layer (>= 1)                */
   int32_t layers;    /* number of hidden layers (1..8)                    */
   int32_t max_batch; /* largest training or rollout batch (>= 1)          */
+  int32_t skip;      /* 1: linear skip path (see above), 0: plain MLP     */
 } ttnn_config;
 
 /* Number of parameters (floats) in the flat layout. */
@@ -80,16 +88,24 @@ int ttnn_build(const ttnn_config* cfg, const float* host_params, void* dev_ws, s
  * *written. */
 int ttnn_conditioning(const ttns_star_model* model, float* host_out, int32_t n_out, int32_t* written);
 
+/* Free propagator U = exp(-i H_S dt) of a star model's electronic system
+ * Hamiltonian (host, FP64 scaling and squaring of a Taylor series, rounded
+ * to FP32): 2 n^2 floats, (re, im) row-major; n_out >= 2 n^2.  dt is in the
+ * Hamiltonian's inverse energy unit (as ttns_tdvp_step's dt). */
+int ttnn_propagator(const ttns_star_model* model, double dt, float* host_out, int32_t n_out);
+
 /* Encode `count` RDMs (device, count x n x n complex, (re, im) doubles,
  * row-major) into dev_out (device, count x n^2 floats). */
 int ttnn_encode(ttnn_net* net, const double* dev_rdm, int64_t count, float* dev_out);
 
 /* Training data: n_sets encoded trajectories of n_times RDMs each (device,
- * n_sets x n_times x n^2 floats) and their conditioning (device,
- * n_sets x n_cond floats).  The arrays stay the caller's and must outlive
- * the training calls that use them. */
-int ttnn_set_data(ttnn_net* net, const float* dev_traj, const float* dev_cond, int32_t n_sets,
-                  int32_t n_times);
+ * n_sets x n_times x n^2 floats), their conditioning (device,
+ * n_sets x n_cond floats) and their free propagators (device,
+ * n_sets x 2 n^2 floats from ttnn_propagator, or NULL for the identity).
+ * The arrays stay the caller's and must outlive the training calls that use
+ * them. */
+int ttnn_set_data(ttnn_net* net, const float* dev_traj, const float* dev_cond, const float* dev_prop,
+                  int32_t n_sets, int32_t n_times);
 
 /* Loss and gradient of one batch without an update.  host_samples holds
  * `batch` pairs (set, t) with window-1 <= t < n_times-1 (the pair predicts
@@ -117,10 +133,11 @@ int ttnn_set_params(ttnn_net* net, const float* host_in);
 
 /* Autoregressive rollout of `batch` sets for n_steps steps.  dev_init:
  * batch x window x n^2 floats (the last `window` encoded RDMs, oldest
- * first), dev_cond: batch x n_cond, dev_out: batch x n_steps x n^2 (the
- * predicted, trace-normalised RDMs).  Asynchronous. */
-int ttnn_rollout(ttnn_net* net, const float* dev_init, const float* dev_cond, int32_t batch,
-                 int32_t n_steps, float* dev_out);
+ * first), dev_cond: batch x n_cond, dev_prop: batch x 2 n^2 (or NULL, as
+ * in training), dev_out: batch x n_steps x n^2 (the predicted,
+ * trace-normalised RDMs).  Asynchronous. */
+int ttnn_rollout(ttnn_net* net, const float* dev_init, const float* dev_cond, const float* dev_prop,
+                 int32_t batch, int32_t n_steps, float* dev_out);
 
 /* Judge rollouts against reference (TTNS) trajectories, both encoded
  * (device, batch x n_steps x n^2): dev_dist[b][t] = trace distance

@@ -62,6 +62,15 @@ extern "C" {
                                   fit the tiles; by default only nodes of at
                                   least 16384 entries use it (smaller ones are
                                   latency-bound and keep the scalar FP64 apply) */
+#define TTNS_FLAG_AUTOTUNE 2u  /* wide executor: at build, time the H_eff
+                                  variants of every node class (scalar apply,
+                                  matrix-core small or large tile) and the QR
+                                  variants of every tall QR shape (one
+                                  workgroup, or 1/2x, 1x, 2x the default
+                                  workgroup count) on the initial state, and
+                                  plan the step with the fastest of each;
+                                  ttns_tuning_report lists the choices.  The
+                                  build then runs the initial programs twice. */
 
 /* observables (ttns_observe kinds) */
 #define TTNS_OBS_RDM 0       /* root reduced density matrix, n x n complex:
@@ -222,6 +231,12 @@ int ttns_profile_read(ttns_ctx *ctx, int32_t reset, double *avg_ms,
                       int64_t *launches, double *flops_per_launch);
 int ttns_profile_kernel(ttns_ctx *ctx, int32_t kernel, double *total_ms,
                         int64_t *launches, double *flops, double *bytes);
+
+/* Text report of the autotuner's measurements and choices (empty without
+ * TTNS_FLAG_AUTOTUNE): one line per node class or QR shape.  Writes at most
+ * n bytes including the terminating zero; *needed (optional) receives the
+ * full length + 1. */
+int ttns_tuning_report(const ttns_ctx* ctx, char* out, size_t n, size_t* needed);
 
 int ttns_destroy(ttns_ctx *ctx);
 const char *ttns_last_error(void);

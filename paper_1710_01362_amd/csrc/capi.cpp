@@ -4,6 +4,7 @@
 // tree) and the C-ABI entry points of include/ttns.h.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -96,6 +97,7 @@ struct TreeState {
   // H_eff on the matrix cores (empty: the node uses the scalar apply)
   std::vector<std::vector<int>> mode_pre;     // bond-bond pre-stages (ModeDesc ids)
   std::vector<std::vector<int>> mode_groups;  // groups; the first carries the site term
+  std::vector<int> mode_tile;                 // 0 default, 1 small, 2 large tile (autotuner)
 };
 
 bool in_subtree(const TreeState& t, int node, int v) { return node >= v && node < v + t.sub[v]; }
@@ -227,6 +229,12 @@ struct ttns_ctx {
   double last_h = -1e300;
   int scratch_desc = 0;  // first of the descriptor slots ttns_apply_heff rewrites
   std::vector<double> step_flops, heff_flops;  // per tree, algorithmic
+  // autotuner: the probe build plans every candidate; the final build
+  // follows the measured choices
+  bool tune_probe = false;
+  std::map<std::string, int> tune_heff;  // node class -> 0 scalar, 1 small tile, 2 large tile
+  std::map<std::string, int> tune_qr;    // QR shape -> 0 one workgroup, k > 0 wide with k workgroups
+  std::string tune_report;
 };
 
 namespace {
@@ -636,18 +644,36 @@ struct Builder {
   }
 
   // H_eff at v as matrix-core groups; false when v does not qualify.
+  // node class of the autotuner: shape, physical axis and term structure
+  std::string heff_key(int v, const ApplyDesc& d, size_t n_pre) const {
+    const Shape& sh = t.shape[v];
+    std::string k = "node";
+    for (int a = 0; a < sh.rank; ++a) k += (a ? "x" : " ") + std::to_string(sh.dims[a]);
+    k += " phys" + std::to_string(sh.phys_axis) + " terms" + std::to_string(d.n_entries) + "/" +
+         std::to_string(n_pre);
+    return k;
+  }
+
   bool plan_mode_groups(int v) {
     const int prec = c.opts.precision;
     if (c.persistent) return false;  // the one-workgroup executor keeps the scalar apply
     const Shape& sh = t.shape[v];
-    if (sh.size < kMfmaMinSize && !(c.opts.flags & TTNS_FLAG_MFMA_ALL))
-      return false;  // small nodes: latency-bound, scalar FP64 apply
     const int maxD = mode_max_bond(prec);
     for (int a = 0; a < sh.rank; ++a)
       if (a != sh.phys_axis && sh.dims[a] > maxD) return false;
     std::vector<ApplyDesc> pre;
     ApplyDesc d = make_sum(v, -2, t.T[v], t.dev.W, pre);
     if (d.n_entries == 0) return false;
+    t.mode_tile[v] = 0;
+    if (!c.tune_probe) {
+      auto it = c.tune_heff.find(heff_key(v, d, pre.size()));
+      if (it != c.tune_heff.end()) {
+        if (it->second == 0) return false;
+        t.mode_tile[v] = it->second;
+      } else if (sh.size < kMfmaMinSize && !(c.opts.flags & TTNS_FLAG_MFMA_ALL)) {
+        return false;  // small nodes: latency-bound, scalar FP64 apply
+      }
+    }
     auto blank = [&](const cd* src, cd* y) {
       ModeDesc m{};
       m.sh = sh;
@@ -757,6 +783,7 @@ struct Builder {
       o.n = m.n_rest;
       o.axis = m.sh.dims[m.sh.phys_axis];
       o.j = mode_padded(m.prec, m.sh.dims[m.axis]);
+      o.i1 = t.mode_tile[v];
       out.push_back(o);
     }
     for (int id : t.mode_groups[v]) {
@@ -770,6 +797,7 @@ struct Builder {
       o.n = m.n_rest;
       o.axis = m.sh.dims[m.sh.phys_axis];
       o.j = mode_padded(m.prec, m.sh.dims[m.axis]);
+      o.i1 = t.mode_tile[v];
       out.push_back(o);
     }
   }
@@ -830,6 +858,7 @@ struct Builder {
     t.heff_pre.assign(t.n, {});
     t.mode_pre.assign(t.n, {});
     t.mode_groups.assign(t.n, {});
+    t.mode_tile.assign(t.n, 0);
     for (int v = 0; v < t.n; ++v) {
       t.heff_desc[v] = sum_desc(v, -2, t.T[v], t.dev.W, t.heff_pre[v]);
       plan_mode_groups(v);
@@ -908,12 +937,22 @@ struct Builder {
     // one workgroup (LDS-resident, or streaming through L2 up to
     // kQrOneGroupRows rows); taller matrices split rows over workgroups with
     // one launch per phase and column
-    if ((size_t)rows * (cols + 2) <= (size_t)kQrLdsEntries || rows <= kQrOneGroupRows) {
+    const bool lds = (size_t)rows * (cols + 2) <= (size_t)kQrLdsEntries;
+    int choice = -1;  // -1: default rule
+    if (!lds && !c.tune_probe) {
+      auto it = c.tune_qr.find(qr_key(rows, cols));
+      if (it != c.tune_qr.end()) choice = it->second;
+    }
+    if (lds || choice == 0 || (choice < 0 && rows <= kQrOneGroupRows)) {
       out.push_back(o);
       return;
     }
+    push_wide_qr(out, o, cols, choice > 0 ? choice : qr_wide_default(rows));
+  }
+  // the launches of a wide QR with nvb workgroups (o: the OP_QR op)
+  static void push_wide_qr(std::vector<Op>& out, Op o, int cols, int nvb) {
     o.type = OP_QRW;
-    o.nvb = std::min(kMaxQrVb, std::max(1, (rows + 511) / 512));
+    o.nvb = nvb;
     o.i0 = 0;
     out.push_back(o);
     for (int k = 0; k < cols; ++k)
@@ -927,6 +966,10 @@ struct Builder {
     out.push_back(o);
   }
   void qr(int u, int w) { qr_axis(u, axis_of(t, u, w)); }
+  static std::string qr_key(int rows, int cols) {
+    return "qr " + std::to_string(rows) + "x" + std::to_string(cols);
+  }
+  static int qr_wide_default(int rows) { return std::min(kMaxQrVb, std::max(1, (rows + 511) / 512)); }
 
   // x (node v's tensor or the absorb buffer) -> T[v] = exp(-i h H_eff) x
   void evolve_node(int v, const cd* x) {
@@ -1267,7 +1310,7 @@ int prepare(ttns_ctx& c, std::vector<TreeState>&& trees, const ttns_opts* opts, 
   if (!(o.rank_tol > 0) || !(o.breakdown_tol > 0)) return fail(TTNS_EINVAL, "tolerances must be > 0");
   if (o.precision < TTNS_FP64 || o.precision > TTNS_BF16X3) return fail(TTNS_EINVAL, "bad precision");
   if (o.executor < TTNS_EXEC_AUTO || o.executor > TTNS_EXEC_PERSISTENT) return fail(TTNS_EINVAL, "bad executor");
-  if (o.flags & ~TTNS_FLAG_MFMA_ALL) return fail(TTNS_EINVAL, "unknown option flags");
+  if (o.flags & ~(TTNS_FLAG_MFMA_ALL | TTNS_FLAG_AUTOTUNE)) return fail(TTNS_EINVAL, "unknown option flags");
   c.opts = o;
   c.trees = std::move(trees);
   c.persistent = (o.executor == TTNS_EXEC_PERSISTENT) ||
@@ -1376,7 +1419,8 @@ int prepare(ttns_ctx& c, std::vector<TreeState>&& trees, const ttns_opts* opts, 
   c.o_modes = take(c.modes.size() * sizeof(ModeDesc));
   c.o_bonds = take(c.bonds.size() * sizeof(BondDesc));
   c.o_trees = take(c.trees.size() * sizeof(TreeDev));
-  c.o_prog = take(persistent_prog.size() * sizeof(Op));
+  // the op table is read only by the persistent executor
+  c.o_prog = take(c.persistent ? persistent_prog.size() * sizeof(Op) : 0);
   c.o_begin = take(c.trees.size() * sizeof(int));
   c.o_end = take(c.trees.size() * sizeof(int));
   c.total = align256(off);
@@ -1426,7 +1470,8 @@ int prepare(ttns_ctx& c, std::vector<TreeState>&& trees, const ttns_opts* opts, 
   if ((rc = upload(c, c.o_modes, c.modes.data(), c.modes.size() * sizeof(ModeDesc)))) return rc;
   if ((rc = upload(c, c.o_bonds, c.bonds.data(), c.bonds.size() * sizeof(BondDesc)))) return rc;
   if ((rc = upload(c, c.o_trees, tdev.data(), tdev.size() * sizeof(TreeDev)))) return rc;
-  if ((rc = upload(c, c.o_prog, persistent_prog.data(), persistent_prog.size() * sizeof(Op)))) return rc;
+  if (c.persistent)
+    if ((rc = upload(c, c.o_prog, persistent_prog.data(), persistent_prog.size() * sizeof(Op)))) return rc;
   if ((rc = upload(c, c.o_begin, c.tree_begin.data(), c.tree_begin.size() * sizeof(int)))) return rc;
   if ((rc = upload(c, c.o_end, c.tree_end.data(), c.tree_end.size() * sizeof(int)))) return rc;
   if ((rc = set_half(c, 0.0))) return rc;
@@ -1532,7 +1577,8 @@ int validate_program(ttns_ctx& c, const std::vector<Op>& ops, bool allow_user_xy
         }
         if (m.axis == m.sh.phys_axis || D > mode_max_bond(m.prec) || o.n != m.n_rest ||
             o.axis != dp || o.i0 != m.prec || m.n_e < 1 || m.n_e > kMaxGroup ||
-            o.j != mode_padded(m.prec, D))
+            o.j != mode_padded(m.prec, D) || o.i1 < 0 || o.i1 > 2 ||
+            (o.i1 == 1 && o.j > mode_small_dp(m.prec)))
           rc.err = "internal: matrix-core group";
         break;
       }
@@ -1686,6 +1732,7 @@ int ttns_workspace_size(const ttns_tree* trees, int32_t n_trees, const ttns_opts
   auto ts = trees_from_api(trees, n_trees, err, rc);
   if (rc) return fail(rc, err);
   ttns_ctx c;
+  c.tune_probe = opts && (opts->flags & TTNS_FLAG_AUTOTUNE);  // the probe plan is the larger
   return prepare(c, std::move(ts), opts, nullptr, 0, nullptr, true, bytes);
 }
 
@@ -1696,7 +1743,150 @@ int ttns_star_workspace_size(const ttns_star_model* models, int32_t n, const ttn
   auto ts = trees_from_star(models, n, err, rc);
   if (rc) return fail(rc, err);
   ttns_ctx c;
+  c.tune_probe = opts && (opts->flags & TTNS_FLAG_AUTOTUNE);  // the probe plan is the larger
   return prepare(c, std::move(ts), opts, nullptr, 0, nullptr, true, bytes);
+}
+
+// Mean time of one pass of `ops` on the context's stream (after one
+// untimed pass), with the range checker run first.
+static int time_ops(ttns_ctx& c, const std::vector<Op>& ops, int reps, double& ms) {
+  int rc = validate_program(c, ops, false);
+  if (rc) return rc;
+  if ((rc = run_ops(c, ops))) return rc;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  hipError_t err = hipEventRecord(e0, c.stream);
+  for (int r = 0; r < reps && err == hipSuccess; ++r)
+    for (const Op& o : ops) {
+      err = launch_op(o, c.tables, c.stream);
+      if (err != hipSuccess) break;
+    }
+  if (err == hipSuccess) err = hipEventRecord(e1, c.stream);
+  if (err == hipSuccess) err = hipEventSynchronize(e1);
+  float t = 0.f;
+  if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != hipSuccess) return fail(TTNS_EDEVICE, std::string("autotune timing: ") + hipGetErrorString(err));
+  ms = t / reps;
+  return TTNS_OK;
+}
+
+// The autotuner, run on a probe build whose plan holds every candidate:
+// for each node class the H_eff apply of one Lanczos iteration (scalar
+// gather kernel, or matrix-core groups with the small or the large tile)
+// and for each tall QR shape the QR of a copy of a real node tensor (one
+// workgroup, or the wide QR with 1/2, 1 and 2 times its default workgroup
+// count), timed on the initial state; the fastest candidate is kept.
+static int autotune(ttns_ctx& c) {
+  constexpr int kReps = 5;
+  char line[256];
+  std::string rep;
+  for (size_t ti = 0; ti < c.trees.size(); ++ti) {
+    TreeState& t = c.trees[ti];
+    std::vector<Op> ops;
+    Builder b{c, t, (int)ti, ops};
+    for (int v = 0; v < t.n; ++v) {
+      if (t.mode_groups[v].empty()) continue;  // no matrix-core candidate
+      std::vector<ApplyDesc> pre;
+      const ApplyDesc d = b.make_sum(v, -2, t.T[v], t.dev.W, pre);
+      const std::string key = b.heff_key(v, d, pre.size());
+      if (c.tune_heff.count(key)) continue;
+      const int n = t.shape[v].size;
+      const int j = std::min(t.kmax, n) / 2;  // a mid-Lanczos iteration
+      const cd* vj = t.dev.V + (size_t)j * t.dev.ldv;
+      auto lz = [&](int mfma) {
+        Op o = b.base(OP_APPLY_LZ, Builder::nvb_of(n));
+        o.desc = t.heff_desc[v];
+        o.j = j;
+        o.n = n;
+        o.i0 = mfma;
+        ops.push_back(o);
+      };
+      double best = 0.0, ms = 0.0;
+      int choice = 0, rc;
+      ops.clear();
+      for (int p : t.heff_pre[v]) b.apply_op(p, vj);
+      lz(0);
+      if ((rc = time_ops(c, ops, kReps, ms))) return rc;
+      best = ms;
+      snprintf(line, sizeof line, "%s: scalar %.4f ms", key.c_str(), ms);
+      std::string l = line;
+      bool small_fits = true;
+      for (int id : t.mode_groups[v]) {
+        const ModeDesc& m = c.modes[id];
+        small_fits = small_fits && mode_padded(m.prec, m.sh.dims[m.axis]) <= mode_small_dp(m.prec);
+      }
+      for (int tile = small_fits ? 1 : 2; tile <= 2; ++tile) {
+        t.mode_tile[v] = tile;
+        ops.clear();
+        b.mode_apply(v, vj, t.dev.W);
+        lz(1);
+        if ((rc = time_ops(c, ops, kReps, ms))) return rc;
+        snprintf(line, sizeof line, ", matrix cores %s tile %.4f ms", tile == 1 ? "small" : "large", ms);
+        l += line;
+        if (ms < best) {
+          best = ms;
+          choice = tile;
+        }
+      }
+      t.mode_tile[v] = 0;
+      c.tune_heff[key] = choice;
+      rep += l + " -> " + (choice == 0 ? "scalar" : choice == 1 ? "small tile" : "large tile") + "\n";
+    }
+  }
+  // tall QR shapes of the step programs
+  for (const Op& q : c.step_ops) {
+    if (!(q.type == OP_QR || (q.type == OP_QRW && q.i0 == 0))) continue;
+    const Shape& sh = c.descs[q.desc].sh;
+    const int cols = sh.dims[q.axis], rows = sh.size / cols;
+    if ((size_t)rows * (cols + 2) <= (size_t)kQrLdsEntries) continue;
+    const std::string key = Builder::qr_key(rows, cols);
+    if (c.tune_qr.count(key)) continue;
+    TreeState& t = c.trees[q.tree];
+    Op base = q;
+    base.type = OP_QR;
+    base.nvb = 1;
+    base.i0 = 0;
+    base.j = 0;
+    Op cp{};
+    cp.type = OP_COPY;
+    cp.tree = q.tree;
+    cp.desc = -1;
+    cp.n = sh.size;
+    cp.nvb = Builder::nvb_of(sh.size);
+    cp.p0 = q.p1;
+    cp.p1 = t.dev.X;
+    base.p1 = t.dev.X;
+    const int def = Builder::qr_wide_default(rows);
+    std::vector<int> cand{0};
+    for (int k : {std::max(1, def / 2), def, std::min(kMaxQrVb, 2 * def)})
+      if (std::find(cand.begin(), cand.end(), k) == cand.end()) cand.push_back(k);
+    double best = 0.0;
+    int choice = 0;
+    std::string l = key + ":";
+    for (size_t i = 0; i < cand.size(); ++i) {
+      std::vector<Op> ops{cp};
+      if (cand[i] == 0) ops.push_back(base);
+      else Builder::push_wide_qr(ops, base, cols, cand[i]);
+      double ms = 0.0;
+      int rc = time_ops(c, ops, 3, ms);
+      if (rc) return rc;
+      if (cand[i] == 0) snprintf(line, sizeof line, " one workgroup %.4f ms", ms);
+      else snprintf(line, sizeof line, ", wide x%d %.4f ms", cand[i], ms);
+      l += line;
+      if (i == 0 || ms < best) {
+        best = ms;
+        choice = cand[i];
+      }
+    }
+    c.tune_qr[key] = choice;
+    rep += l + " -> " + (choice == 0 ? std::string("one workgroup") : "wide x" + std::to_string(choice)) + "\n";
+  }
+  HIPCHK(hipStreamSynchronize(c.stream));
+  c.tune_report = rep;
+  return TTNS_OK;
 }
 
 static int build_common(std::vector<TreeState>&& ts, const ttns_opts* opts, void* ws, size_t ws_bytes,
@@ -1705,7 +1895,22 @@ static int build_common(std::vector<TreeState>&& ts, const ttns_opts* opts, void
   *out = nullptr;
   std::unique_ptr<ttns_ctx> c(new ttns_ctx());
   size_t dummy = 0;
-  int rc = prepare(*c, std::move(ts), opts, ws, ws_bytes, stream, false, &dummy);
+  int rc;
+  if (opts && (opts->flags & TTNS_FLAG_AUTOTUNE)) {
+    // probe build with every candidate planned, measure, then the real build
+    std::vector<TreeState> copy = ts;
+    std::unique_ptr<ttns_ctx> probe(new ttns_ctx());
+    probe->tune_probe = true;
+    rc = prepare(*probe, std::move(ts), opts, ws, ws_bytes, stream, false, &dummy);
+    if (!rc && !probe->persistent) rc = autotune(*probe);
+    c->tune_heff = probe->tune_heff;
+    c->tune_qr = probe->tune_qr;
+    c->tune_report = probe->tune_report;
+    (void)ttns_destroy(probe.release());
+    if (rc) return rc;
+    ts = std::move(copy);
+  }
+  rc = prepare(*c, std::move(ts), opts, ws, ws_bytes, stream, false, &dummy);
   if (rc) {
     if (c->cap) (void)hipStreamDestroy(c->cap);
     return rc;
@@ -1897,6 +2102,17 @@ int ttns_profile_kernel(ttns_ctx* c, int32_t kernel, double* total_ms, int64_t* 
   if (launches) *launches = c->cls_n[kernel];
   if (flops) *flops = c->cls_flops[kernel];
   if (bytes) *bytes = c->cls_bytes[kernel];
+  return TTNS_OK;
+}
+
+int ttns_tuning_report(const ttns_ctx* c, char* out, size_t n, size_t* needed) {
+  if (!c || (!out && n > 0)) return fail(TTNS_EINVAL, "ttns_tuning_report: bad arguments");
+  if (needed) *needed = c->tune_report.size() + 1;
+  if (n > 0) {
+    const size_t k = std::min(n - 1, c->tune_report.size());
+    memcpy(out, c->tune_report.data(), k);
+    out[k] = 0;
+  }
   return TTNS_OK;
 }
 

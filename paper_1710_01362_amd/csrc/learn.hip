@@ -14,6 +14,7 @@
 
 #include <algorithm>
 
+#include "device_common.h"
 #include "learn_internal.h"
 
 namespace ttns {
@@ -77,6 +78,9 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
           case EPI_BIAS_RESID:
             v = v + g.bias[n] + g.R[(size_t)m * g.ldr + n];
             break;
+          case EPI_ADD:
+            v = v + g.C[(size_t)m * g.ldc + n];
+            break;
           case EPI_TANH_BACK: {
             const float h = g.R[(size_t)m * g.ldr + n];
             v = v * (1.f - h * h);
@@ -89,22 +93,29 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
       }
 }
 
-// X[b] = [traj[s][t-window+1 .. t] (window x ne) (+ noise[b]), cond[s]],
-// Y[b] = traj[s][t+1]
+// X[b] = [traj[s][t-window+1 .. t] (window x ne) (+ noise[b]), cond[s],
+// (skip) cond[s][c] * x_last[e] for (c, e) row-major], Y[b] = traj[s][t+1]
 __global__ void k_windows(const int* samples, const float* traj, int T, const float* cond, int ne,
-                          int window, int nc, float* X, float* Y, int B, const float* noise) {
+                          int window, int nc, float* X, float* Y, int B, const float* noise, int skip) {
   const int b = blockIdx.x;
   if (b >= B) return;
   const int s = samples[2 * b], t = samples[2 * b + 1];
-  const int in = window * ne + nc;
+  const int wn = window * ne;
+  const int in = wn + nc + (skip ? nc * ne : 0);
   const float* tr = traj + (size_t)s * T * ne;
+  const float* nz = noise ? noise + (size_t)b * wn : nullptr;
   for (int i = threadIdx.x; i < in; i += blockDim.x) {
     float v;
-    if (i < window * ne) {
+    if (i < wn) {
       v = tr[(size_t)(t - window + 1) * ne + i];
-      if (noise) v += noise[(size_t)b * window * ne + i];
+      if (nz) v += nz[i];
+    } else if (i < wn + nc) {
+      v = cond[(size_t)s * nc + (i - wn)];
     } else {
-      v = cond[(size_t)s * nc + (i - window * ne)];
+      const int c = (i - wn - nc) / ne, e = (i - wn - nc) % ne;
+      float last = tr[(size_t)t * ne + e];
+      if (nz) last += nz[(window - 1) * ne + e];
+      v = cond[(size_t)s * nc + c] * last;
     }
     X[(size_t)b * in + i] = v;
   }
@@ -168,10 +179,11 @@ __global__ void k_step_inc(int* step) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *step += 1;
 }
 
-// Rollout: prediction -> decode -> divide by the trace -> encode -> output
-// and window shift (X rows: [window x ne | cond]).
-__global__ void k_rollout_post(const float* P, float* X, int B, int ne, int n, int window, int in,
-                               float* out, int n_steps, int step) {
+// Rollout: prediction -> divide by the trace -> output and window shift
+// (X rows: [window x ne | cond | (skip) cond x last]); the bilinear block
+// is recomputed from the new last RDM.
+__global__ void k_rollout_post(const float* P, float* X, int B, int ne, int n, int window, int nc, int skip,
+                               int in, float* out, int n_steps, int step) {
   const int b = blockIdx.x;
   if (b >= B) return;
   __shared__ float tr;
@@ -196,6 +208,12 @@ __global__ void k_rollout_post(const float* P, float* X, int B, int ne, int n, i
     const float e = P[(size_t)b * ne + i] * inv;
     x[(window - 1) * ne + i] = e;
     out[((size_t)b * n_steps + step) * ne + i] = e;
+  }
+  if (skip) {
+    __syncthreads();
+    const int wn = window * ne;
+    for (int i = threadIdx.x; i < nc * ne; i += blockDim.x)
+      x[wn + nc + i] = x[wn + i / ne] * x[(window - 1) * ne + i % ne];
   }
 }
 
@@ -271,12 +289,20 @@ __global__ void k_judge(const float* dist, int B, int T, float tol, int* accept,
   accept[b] = mx <= tol ? 1 : 0;
 }
 
-// X[b] = [init[b] (window x ne), cond[b]]
-__global__ void k_rollout_init(const float* init, const float* cond, int ne, int window, int nc, float* X) {
+// X[b] = [init[b] (window x ne), cond[b], (skip) cond[b] x last of init[b]]
+__global__ void k_rollout_init(const float* init, const float* cond, int ne, int window, int nc, int skip, float* X) {
   const int b = blockIdx.x;
-  const int in = window * ne + nc;
-  for (int i = threadIdx.x; i < in; i += blockDim.x)
-    X[(size_t)b * in + i] = i < window * ne ? init[(size_t)b * window * ne + i] : cond[(size_t)b * nc + i - window * ne];
+  const int wn = window * ne;
+  const int in = wn + nc + (skip ? nc * ne : 0);
+  const float* w = init + (size_t)b * wn;
+  const float* c = cond + (size_t)b * nc;
+  for (int i = threadIdx.x; i < in; i += blockDim.x) {
+    float v;
+    if (i < wn) v = w[i];
+    else if (i < wn + nc) v = c[i - wn];
+    else v = c[(i - wn - nc) / ne] * w[(window - 1) * ne + (i - wn - nc) % ne];
+    X[(size_t)b * in + i] = v;
+  }
 }
 
 // rdm: count x n x n complex (re, im doubles, row-major) -> n^2 reals
@@ -315,6 +341,52 @@ __global__ void k_select(const float* pred, const float* ref, const int* accept,
   }
 }
 
+// out[b] = enc(U rho U^dagger), rho = decoded row b of src (row stride
+// `stride`, n^2 reals), U = the n x n complex propagator (2 n^2 floats,
+// (re, im) row-major) of set samples[2b] (training) or of row b (samples
+// null).  One workgroup of 64 threads per row, thread (j, k) = entry jk.
+__global__ void k_propagate(const float* src, int stride, const int* samples, const float* U, int n, float* out) {
+  const int b = blockIdx.x;
+  const int t = threadIdx.x, j = t / n, k = t % n;
+  const int ne = n * n, m = n * (n - 1) / 2;
+  __shared__ double2 rho[64], u[64], mu[64];
+  const int set = samples ? samples[2 * b] : b;
+  const float* r = src + (size_t)b * stride;
+  const float* uu = U + (size_t)set * 2 * ne;
+  const bool on = t < ne;
+  // upper-triangle index of (min, max) pair, row-major
+  auto q_of = [&](int a, int c) { return a * n - a * (a + 1) / 2 + (c - a - 1); };
+  if (on) {
+    double2 v;
+    if (j == k) v = make_double2(r[j], 0.0);
+    else if (j < k) v = make_double2(r[n + q_of(j, k)], r[n + m + q_of(j, k)]);
+    else v = make_double2(r[n + q_of(k, j)], -r[n + m + q_of(k, j)]);
+    rho[t] = v;
+    u[t] = make_double2(uu[2 * t], uu[2 * t + 1]);
+  }
+  __syncthreads();
+  if (on) {  // (U rho)[j][k]
+    double2 acc = make_double2(0.0, 0.0);
+    for (int l = 0; l < n; ++l) acc = cfma(u[j * n + l], rho[l * n + k], acc);
+    mu[t] = acc;
+  }
+  __syncthreads();
+  if (on) {  // (U rho U^dagger)[j][k] = sum_l (U rho)[j][l] conj(U[k][l])
+    double2 acc = make_double2(0.0, 0.0);
+    for (int l = 0; l < n; ++l) {
+      const double2 a = mu[j * n + l], c = u[k * n + l];
+      acc.x += a.x * c.x + a.y * c.y;
+      acc.y += a.y * c.x - a.x * c.y;
+    }
+    float* o = out + (size_t)b * ne;
+    if (j == k) o[j] = (float)acc.x;
+    else if (j < k) {
+      o[n + q_of(j, k)] = (float)acc.x;
+      o[n + m + q_of(j, k)] = (float)acc.y;
+    }
+  }
+}
+
 // ---------------------------------------------------------------- launchers
 hipError_t learn_gemm(const GemmArgs& g, hipStream_t s) {
   const dim3 grid((g.N + GT - 1) / GT, (g.M + GT - 1) / GT);
@@ -322,8 +394,10 @@ hipError_t learn_gemm(const GemmArgs& g, hipStream_t s) {
   return hipGetLastError();
 }
 hipError_t learn_windows(const int* samples, const float* traj, int T, const float* cond, int ne,
-                         int window, int nc, float* X, float* Y, int B, const float* noise, hipStream_t s) {
-  hipLaunchKernelGGL(k_windows, dim3(B), dim3(256), 0, s, samples, traj, T, cond, ne, window, nc, X, Y, B, noise);
+                         int window, int nc, float* X, float* Y, int B, const float* noise, int skip,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_windows, dim3(B), dim3(256), 0, s, samples, traj, T, cond, ne, window, nc, X, Y, B, noise,
+                     skip);
   return hipGetLastError();
 }
 hipError_t learn_loss(const float* P, const float* Y, int n, float* G, float* partial, int nb, float* loss,
@@ -342,18 +416,24 @@ hipError_t learn_adam(float* p, const float* g, float* m, float* v, long long n,
   hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, g, m, v, n, step, lr);
   return hipGetLastError();
 }
-hipError_t learn_rollout_post(const float* P, float* X, int B, int ne, int n, int window, int in, float* out,
-                              int n_steps, int step, hipStream_t s) {
-  hipLaunchKernelGGL(k_rollout_post, dim3(B), dim3(256), 0, s, P, X, B, ne, n, window, in, out, n_steps, step);
+hipError_t learn_rollout_post(const float* P, float* X, int B, int ne, int n, int window, int nc, int skip, int in,
+                              float* out, int n_steps, int step, hipStream_t s) {
+  hipLaunchKernelGGL(k_rollout_post, dim3(B), dim3(256), 0, s, P, X, B, ne, n, window, nc, skip, in, out, n_steps,
+                     step);
   return hipGetLastError();
 }
 hipError_t learn_trace_distance(const float* a, const float* b, int count, int n, float* dist, hipStream_t s) {
   hipLaunchKernelGGL(k_trace_distance, dim3((count + 127) / 128), dim3(128), 0, s, a, b, count, n, dist);
   return hipGetLastError();
 }
-hipError_t learn_rollout_init(const float* init, const float* cond, int B, int ne, int window, int nc, float* X,
-                              hipStream_t s) {
-  hipLaunchKernelGGL(k_rollout_init, dim3(B), dim3(256), 0, s, init, cond, ne, window, nc, X);
+hipError_t learn_rollout_init(const float* init, const float* cond, int B, int ne, int window, int nc, int skip,
+                              float* X, hipStream_t s) {
+  hipLaunchKernelGGL(k_rollout_init, dim3(B), dim3(256), 0, s, init, cond, ne, window, nc, skip, X);
+  return hipGetLastError();
+}
+hipError_t learn_propagate(const float* src, int stride, const int* samples, const float* U, int n, int B,
+                           float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_propagate, dim3(B), dim3(64), 0, s, src, stride, samples, U, n, out);
   return hipGetLastError();
 }
 hipError_t learn_encode(const double* rdm, long long count, int n, float* out, hipStream_t s) {

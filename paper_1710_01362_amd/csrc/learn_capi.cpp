@@ -2,6 +2,8 @@
 // sequences of training (forward, loss, backward, Adam), rollout and
 // judging, and the C-ABI entry points of include/ttnn.h.
 #include <algorithm>
+#include <cmath>
+#include <complex>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -22,6 +24,7 @@ struct ttnn_net {
   int ne = 0, in0 = 0;
   std::vector<int> sizes;                  // layer widths, input first
   std::vector<int64_t> w_off, b_off;       // flat offsets of W and b per layer
+  int64_t s_off = -1;                      // flat offset of the skip matrix W_s
   int64_t n_params = 0;
   hipStream_t stream = nullptr;
   // device buffers inside the caller's workspace
@@ -32,9 +35,11 @@ struct ttnn_net {
   std::vector<float*> H;
   float* dH[2] = {nullptr, nullptr};
   float *lpart = nullptr, *loss = nullptr;
+  float* Rres = nullptr;  // residual base enc(U rho_t U^dagger) of every row
   // training data (caller's device arrays)
   const float* traj = nullptr;
   const float* cond = nullptr;
+  const float* prop = nullptr;  // per-set free propagators, or null
   int n_sets = 0, n_times = 0;
 };
 
@@ -45,9 +50,12 @@ size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 int check_config(const ttnn_config* c) {
   if (!c) return set_error(TTNS_EINVAL, "ttnn: null config");
   if (c->n_levels < 1 || c->n_levels > 8) return set_error(TTNS_EINVAL, "ttnn: n_levels must be in [1, 8]");
-  if (c->window < 1 || c->n_cond < 0 || c->hidden < 1 || c->layers < 1 || c->layers > 8 || c->max_batch < 1)
-    return set_error(TTNS_EINVAL, "ttnn: window, hidden, max_batch >= 1, n_cond >= 0, layers in [1, 8]");
-  const int64_t in0 = (int64_t)c->window * c->n_levels * c->n_levels + c->n_cond;
+  if (c->window < 1 || c->n_cond < 0 || c->hidden < 1 || c->layers < 1 || c->layers > 8 || c->max_batch < 1 ||
+      c->skip < 0 || c->skip > 1)
+    return set_error(TTNS_EINVAL,
+                     "ttnn: window, hidden, max_batch >= 1, n_cond >= 0, layers in [1, 8], skip 0 or 1");
+  const int64_t ne = (int64_t)c->n_levels * c->n_levels;
+  const int64_t in0 = c->window * ne + c->n_cond + (c->skip ? c->n_cond * ne : 0);
   if (in0 > (1 << 20) || c->hidden > (1 << 16) || (int64_t)c->max_batch * std::max<int64_t>(in0, c->hidden) > (1ll << 30))
     return set_error(TTNS_EINVAL, "ttnn: network too large");
   return TTNS_OK;
@@ -57,7 +65,7 @@ int check_config(const ttnn_config* c) {
 // pointers when base is not null.
 size_t layout(const ttnn_config& c, char* base, ttnn_net* net) {
   const int ne = c.n_levels * c.n_levels;
-  const int in0 = c.window * ne + c.n_cond;
+  const int in0 = c.window * ne + c.n_cond + (c.skip ? c.n_cond * ne : 0);
   std::vector<int> sizes{in0};
   for (int l = 0; l < c.layers; ++l) sizes.push_back(c.hidden);
   sizes.push_back(ne);
@@ -68,6 +76,11 @@ size_t layout(const ttnn_config& c, char* base, ttnn_net* net) {
     np += (int64_t)sizes[l] * sizes[l + 1];
     bo.push_back(np);
     np += sizes[l + 1];
+  }
+  int64_t so = -1;
+  if (c.skip) {
+    so = np;
+    np += (int64_t)ne * in0;
   }
   const size_t B = c.max_batch;
   size_t off = 0;
@@ -92,6 +105,7 @@ size_t layout(const ttnn_config& c, char* base, ttnn_net* net) {
   char* d1 = take(B * c.hidden * 4);
   char* lp = take(kLossBlocks * 4);
   char* ls = take(4);
+  char* rr = take(B * ne * 4);
   if (net) {
     net->cfg = c;
     net->ne = ne;
@@ -99,6 +113,7 @@ size_t layout(const ttnn_config& c, char* base, ttnn_net* net) {
     net->sizes = sizes;
     net->w_off = wo;
     net->b_off = bo;
+    net->s_off = so;
     net->n_params = np;
     net->P = (float*)p;
     net->G = (float*)g;
@@ -116,6 +131,7 @@ size_t layout(const ttnn_config& c, char* base, ttnn_net* net) {
     net->dH[1] = (float*)d1;
     net->lpart = (float*)lp;
     net->loss = (float*)ls;
+    net->Rres = (float*)rr;
   }
   return off;
 }
@@ -141,8 +157,10 @@ GemmArgs gemm(int M, int N, int K, const float* A, int sam, int sak, const float
   return g;
 }
 
-// Forward pass of B rows of X into H[.] and Pout.
-int forward(ttnn_net& n, int B) {
+// Forward pass of B rows of X into H[.] and Pout; the output adds the
+// residual base: Rres when the rows have free propagators, else the last
+// RDM of each row's window.
+int forward(ttnn_net& n, int B, bool propagated) {
   const ttnn_config& c = n.cfg;
   const float* a = n.X;
   int lda = n.in0;
@@ -155,9 +173,13 @@ int forward(ttnn_net& n, int B) {
     lda = c.hidden;
   }
   const int L = c.layers;
+  const float* base = propagated ? n.Rres : n.X + (size_t)(c.window - 1) * n.ne;
+  const int ldb = propagated ? n.ne : n.in0;
   LCHK(learn_gemm(gemm(B, n.ne, c.hidden, a, lda, 1, n.P + n.w_off[L], 1, c.hidden, n.Pout, n.ne, EPI_BIAS_RESID,
-                       n.P + n.b_off[L], n.X + (size_t)(c.window - 1) * n.ne, n.in0),
+                       n.P + n.b_off[L], base, ldb),
                   n.stream));
+  if (c.skip)  // Pout += X W_s^T
+    LCHK(learn_gemm(gemm(B, n.ne, n.in0, n.X, n.in0, 1, n.P + n.s_off, 1, n.in0, n.Pout, n.ne, EPI_ADD), n.stream));
   return TTNS_OK;
 }
 
@@ -165,6 +187,8 @@ int forward(ttnn_net& n, int B) {
 int backward(ttnn_net& n, int B) {
   const ttnn_config& c = n.cfg;
   LCHK(learn_loss(n.Pout, n.Y, B * n.ne, n.dOut, n.lpart, kLossBlocks, n.loss, n.stream));
+  if (c.skip)  // dW_s = dOut^T X
+    LCHK(learn_gemm(gemm(n.ne, n.in0, B, n.dOut, 1, n.ne, n.X, n.in0, 1, n.G + n.s_off, n.in0), n.stream));
   const float* g = n.dOut;
   int ldg = n.ne;
   for (int l = c.layers; l >= 0; --l) {
@@ -198,7 +222,10 @@ int load_batch(ttnn_net& n, const int32_t* host_samples, int batch, const float*
   LCHK(hipMemcpyAsync(n.samples, host_samples, (size_t)batch * 2 * sizeof(int32_t), hipMemcpyHostToDevice,
                       n.stream));
   LCHK(learn_windows(n.samples, n.traj, n.n_times, n.cond, n.ne, n.cfg.window, n.cfg.n_cond, n.X, n.Y, batch,
-                     dev_noise, n.stream));
+                     dev_noise, n.cfg.skip, n.stream));
+  if (n.prop)
+    LCHK(learn_propagate(n.X + (size_t)(n.cfg.window - 1) * n.ne, n.in0, n.samples, n.prop, n.cfg.n_levels, batch,
+                         n.Rres, n.stream));
   return TTNS_OK;
 }
 
@@ -262,6 +289,55 @@ int ttnn_conditioning(const ttns_star_model* m, float* host_out, int32_t n_out, 
   return TTNS_OK;
 }
 
+int ttnn_propagator(const ttns_star_model* m, double dt, float* host_out, int32_t n_out) {
+  if (!m || !m->h_el || m->n_levels < 1 || m->n_levels > 8 || !host_out || !std::isfinite(dt))
+    return set_error(TTNS_EINVAL, "ttnn_propagator: bad arguments");
+  const int n = m->n_levels;
+  if (n_out < 2 * n * n) return set_error(TTNS_EINVAL, "ttnn_propagator: output needs 2 n^2 floats");
+  // exp(-i H dt): scale to 1-norm <= 1/2, Taylor to 24 terms, square back
+  typedef std::complex<double> z;
+  std::vector<z> A(n * n), E(n * n, 0.0), term(n * n), tmp(n * n);
+  double nrm = 0.0;
+  for (int j = 0; j < n; ++j) {
+    double col = 0.0;
+    for (int i = 0; i < n; ++i) col += std::abs(z(m->h_el[i * n + j].re, m->h_el[i * n + j].im)) * std::fabs(dt);
+    nrm = std::max(nrm, col);
+  }
+  int sq = 0;
+  while (nrm > 0.5 && sq < 60) {
+    nrm *= 0.5;
+    ++sq;
+  }
+  const double scale = std::ldexp(dt, -sq);
+  for (int i = 0; i < n * n; ++i) A[i] = z(0.0, -1.0) * z(m->h_el[i].re, m->h_el[i].im) * scale;
+  auto mul = [&](const std::vector<z>& X, const std::vector<z>& Y, std::vector<z>& out) {
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        z acc = 0.0;
+        for (int l = 0; l < n; ++l) acc += X[i * n + l] * Y[l * n + j];
+        out[i * n + j] = acc;
+      }
+  };
+  for (int i = 0; i < n; ++i) E[i * n + i] = 1.0;
+  term = E;
+  for (int k = 1; k <= 24; ++k) {
+    mul(term, A, tmp);
+    for (int i = 0; i < n * n; ++i) {
+      term[i] = tmp[i] / (double)k;
+      E[i] += term[i];
+    }
+  }
+  for (int q = 0; q < sq; ++q) {
+    mul(E, E, tmp);
+    E = tmp;
+  }
+  for (int i = 0; i < n * n; ++i) {
+    host_out[2 * i] = (float)E[i].real();
+    host_out[2 * i + 1] = (float)E[i].imag();
+  }
+  return TTNS_OK;
+}
+
 int ttnn_encode(ttnn_net* n, const double* dev_rdm, int64_t count, float* dev_out) {
   if (!n || count < 0 || (count > 0 && (!dev_rdm || !dev_out))) return set_error(TTNS_EINVAL, "ttnn_encode: bad arguments");
   if (count == 0) return TTNS_OK;
@@ -269,11 +345,13 @@ int ttnn_encode(ttnn_net* n, const double* dev_rdm, int64_t count, float* dev_ou
   return TTNS_OK;
 }
 
-int ttnn_set_data(ttnn_net* n, const float* dev_traj, const float* dev_cond, int32_t n_sets, int32_t n_times) {
+int ttnn_set_data(ttnn_net* n, const float* dev_traj, const float* dev_cond, const float* dev_prop,
+                  int32_t n_sets, int32_t n_times) {
   if (!n || !dev_traj || (n->cfg.n_cond > 0 && !dev_cond) || n_sets < 1 || n_times < n->cfg.window + 1)
     return set_error(TTNS_EINVAL, "ttnn_set_data: need n_sets >= 1 and n_times >= window + 1");
   n->traj = dev_traj;
   n->cond = dev_cond;
+  n->prop = dev_prop;
   n->n_sets = n_sets;
   n->n_times = n_times;
   return TTNS_OK;
@@ -282,7 +360,7 @@ int ttnn_set_data(ttnn_net* n, const float* dev_traj, const float* dev_cond, int
 int ttnn_gradients(ttnn_net* n, const int32_t* host_samples, int32_t batch, float* host_loss, float* host_grad) {
   if (!n || !host_loss) return set_error(TTNS_EINVAL, "ttnn_gradients: null argument");
   int rc = load_batch(*n, host_samples, batch);
-  if (!rc) rc = forward(*n, batch);
+  if (!rc) rc = forward(*n, batch, n->prop != nullptr);
   if (!rc) rc = backward(*n, batch);
   if (rc) return rc;
   if (host_grad)
@@ -295,7 +373,7 @@ int ttnn_gradients(ttnn_net* n, const int32_t* host_samples, int32_t batch, floa
 int ttnn_train_step(ttnn_net* n, const int32_t* host_samples, int32_t batch, float lr, const float* dev_noise) {
   if (!n || !(lr > 0)) return set_error(TTNS_EINVAL, "ttnn_train_step: bad arguments");
   int rc = load_batch(*n, host_samples, batch, dev_noise);
-  if (!rc) rc = forward(*n, batch);
+  if (!rc) rc = forward(*n, batch, n->prop != nullptr);
   if (!rc) rc = backward(*n, batch);
   if (rc) return rc;
   // the next call's sample copy is ordered after these launches on the stream
@@ -328,18 +406,21 @@ int ttnn_set_params(ttnn_net* n, const float* host_in) {
   return TTNS_OK;
 }
 
-int ttnn_rollout(ttnn_net* n, const float* dev_init, const float* dev_cond, int32_t batch, int32_t n_steps,
-                 float* dev_out) {
+int ttnn_rollout(ttnn_net* n, const float* dev_init, const float* dev_cond, const float* dev_prop, int32_t batch,
+                 int32_t n_steps, float* dev_out) {
   if (!n || batch < 1 || batch > n->cfg.max_batch || n_steps < 0 || !dev_init || !dev_out ||
       (n->cfg.n_cond > 0 && !dev_cond))
     return set_error(TTNS_EINVAL, "ttnn_rollout: bad arguments (batch must be in [1, max_batch])");
   const ttnn_config& c = n->cfg;
-  LCHK(learn_rollout_init(dev_init, dev_cond, batch, n->ne, c.window, c.n_cond, n->X, n->stream));
+  LCHK(learn_rollout_init(dev_init, dev_cond, batch, n->ne, c.window, c.n_cond, c.skip, n->X, n->stream));
   for (int s = 0; s < n_steps; ++s) {
-    int rc = forward(*n, batch);
+    if (dev_prop)
+      LCHK(learn_propagate(n->X + (size_t)(c.window - 1) * n->ne, n->in0, nullptr, dev_prop, c.n_levels, batch,
+                           n->Rres, n->stream));
+    int rc = forward(*n, batch, dev_prop != nullptr);
     if (rc) return rc;
-    LCHK(learn_rollout_post(n->Pout, n->X, batch, n->ne, c.n_levels, c.window, n->in0, dev_out, n_steps, s,
-                            n->stream));
+    LCHK(learn_rollout_post(n->Pout, n->X, batch, n->ne, c.n_levels, c.window, c.n_cond, c.skip, n->in0, dev_out,
+                            n_steps, s, n->stream));
   }
   return TTNS_OK;
 }

@@ -37,6 +37,7 @@ typedef double d4v __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 
 int mode_max_bond(int prec) { return prec == TTNS_FP64 ? 48 : 64; }
+int mode_small_dp(int prec) { return prec == TTNS_FP64 ? 48 : 64; }
 int mode_padded(int prec, int D) {
   const int pad = prec == TTNS_BF16X3 ? 32 : 16;
   return (2 * D + pad - 1) / pad * pad;
@@ -312,8 +313,10 @@ __global__ __launch_bounds__(kBlock) void k_mode(Op op, DevTables Tb) {
 
 template <int PREC>
 hipError_t launch_prec(const Op& op, const DevTables& t, hipStream_t s, dim3 grid) {
-  // op.j: padded real operand size DP of this group
-  if (op.j <= Prec<PREC>::SMALL)
+  // op.j: padded real operand size DP of this group; op.i1: tile chosen by
+  // the autotuner (1 small, 2 large) or 0 (the small tile when it fits)
+  const bool small = op.i1 == 1 || (op.i1 == 0 && op.j <= Prec<PREC>::SMALL);
+  if (small)
     hipLaunchKernelGGL((k_mode<PREC, Prec<PREC>::SMALL>), grid, dim3(kBlock), 0, s, op, t);
   else
     hipLaunchKernelGGL((k_mode<PREC, Prec<PREC>::BIG>), grid, dim3(kBlock), 0, s, op, t);

@@ -231,5 +231,7 @@ constexpr int kModeNT = 64;
 int mode_max_bond(int prec);
 // padded real operand size (2D rounded up to the MFMA K granule) of a group
 int mode_padded(int prec, int D);
+// largest padded size the small matrix-core tile takes
+int mode_small_dp(int prec);
 
 }  // namespace ttns

@@ -13,7 +13,8 @@ import numpy as np
 from . import ttns as T
 
 EXPORTED = [
-    "ttnn_param_count", "ttnn_workspace_size", "ttnn_build", "ttnn_conditioning", "ttnn_encode",
+    "ttnn_param_count", "ttnn_workspace_size", "ttnn_build", "ttnn_conditioning", "ttnn_propagator",
+    "ttnn_encode",
     "ttnn_set_data", "ttnn_gradients", "ttnn_train_step", "ttnn_last_loss", "ttnn_get_params",
     "ttnn_set_params", "ttnn_rollout", "ttnn_judge", "ttnn_select", "ttnn_destroy",
 ]
@@ -21,7 +22,8 @@ EXPORTED = [
 
 class Config(C.Structure):
     _fields_ = [("n_levels", C.c_int32), ("window", C.c_int32), ("n_cond", C.c_int32),
-                ("hidden", C.c_int32), ("layers", C.c_int32), ("max_batch", C.c_int32)]
+                ("hidden", C.c_int32), ("layers", C.c_int32), ("max_batch", C.c_int32),
+                ("skip", C.c_int32)]
 
 
 _ready = False
@@ -36,14 +38,15 @@ def lib():
         L.ttnn_workspace_size.argtypes = [C.POINTER(Config), C.POINTER(S)]
         L.ttnn_build.argtypes = [C.POINTER(Config), P, P, S, P, C.POINTER(P)]
         L.ttnn_conditioning.argtypes = [C.POINTER(T.StarModel), P, I, C.POINTER(I)]
+        L.ttnn_propagator.argtypes = [C.POINTER(T.StarModel), C.c_double, P, I]
         L.ttnn_encode.argtypes = [P, P, C.c_int64, P]
-        L.ttnn_set_data.argtypes = [P, P, P, I, I]
+        L.ttnn_set_data.argtypes = [P, P, P, P, I, I]
         L.ttnn_gradients.argtypes = [P, P, I, P, P]
         L.ttnn_train_step.argtypes = [P, P, I, F, P]
         L.ttnn_last_loss.argtypes = [P, P]
         L.ttnn_get_params.argtypes = [P, P]
         L.ttnn_set_params.argtypes = [P, P]
-        L.ttnn_rollout.argtypes = [P, P, P, I, I, P]
+        L.ttnn_rollout.argtypes = [P, P, P, P, I, I, P]
         L.ttnn_judge.argtypes = [P, P, P, I, I, F, P, P, P]
         L.ttnn_select.argtypes = [P, P, P, P, I, I, P]
         L.ttnn_destroy.argtypes = [P]
@@ -53,8 +56,8 @@ def lib():
     return L
 
 
-def config(n_levels, window, n_cond, hidden, layers, max_batch):
-    return Config(n_levels, window, n_cond, hidden, layers, max_batch)
+def config(n_levels, window, n_cond, hidden, layers, max_batch, skip=0):
+    return Config(n_levels, window, n_cond, hidden, layers, max_batch, int(skip))
 
 
 def param_count(cfg):
@@ -79,8 +82,23 @@ def conditioning(model):
     return out[:n.value].copy()
 
 
+def propagator(model, dt):
+    """Free propagator exp(-i H_S dt) of a star model (workload dict) as
+    2 n^2 floats, via the library."""
+    keep = []
+    sm = T.star_model(model, keep)
+    n = int(np.asarray(model["h_el"]).shape[0])
+    out = np.zeros(2 * n * n, dtype=np.float32)
+    T.check(lib().ttnn_propagator(C.byref(sm), C.c_double(dt), out.ctypes.data, out.size))
+    return out
+
+
 def _ptr(t):
     return C.c_void_p(t.data_ptr())
+
+
+def _opt(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
 
 
 class Net:
@@ -125,11 +143,13 @@ class Net:
         T.check(lib().ttnn_encode(self.net, _ptr(src), count, _ptr(out)))
         return out
 
-    def ttnn_set_data(self, traj_dev, cond_dev):
-        """traj_dev: (sets, times, n^2) float32; cond_dev: (sets, n_cond) float32."""
-        self._data = (traj_dev.contiguous(), cond_dev.contiguous())
+    def ttnn_set_data(self, traj_dev, cond_dev, prop_dev=None):
+        """traj_dev: (sets, times, n^2) float32; cond_dev: (sets, n_cond)
+        float32; prop_dev: (sets, 2 n^2) float32 free propagators or None."""
+        self._data = (traj_dev.contiguous(), cond_dev.contiguous(),
+                      None if prop_dev is None else prop_dev.contiguous())
         s, t = traj_dev.shape[0], traj_dev.shape[1]
-        T.check(lib().ttnn_set_data(self.net, _ptr(self._data[0]), _ptr(self._data[1]), s, t))
+        T.check(lib().ttnn_set_data(self.net, _ptr(self._data[0]), _ptr(self._data[1]), _opt(self._data[2]), s, t))
 
     def ttnn_gradients(self, samples):
         samples = np.ascontiguousarray(samples, dtype=np.int32)
@@ -166,14 +186,16 @@ class Net:
         params = np.ascontiguousarray(params, dtype=np.float32)
         T.check(lib().ttnn_set_params(self.net, params.ctypes.data))
 
-    def ttnn_rollout(self, init_dev, cond_dev, n_steps):
-        """init_dev: (B, window, n^2), cond_dev: (B, n_cond) -> (B, n_steps, n^2)."""
+    def ttnn_rollout(self, init_dev, cond_dev, n_steps, prop_dev=None):
+        """init_dev: (B, window, n^2), cond_dev: (B, n_cond), prop_dev:
+        (B, 2 n^2) or None -> (B, n_steps, n^2)."""
         torch = self.torch
         init_dev = init_dev.contiguous()
         cond_dev = cond_dev.contiguous()
+        prop_dev = None if prop_dev is None else prop_dev.contiguous()
         B = init_dev.shape[0]
         out = torch.empty((B, n_steps, self.cfg.n_levels ** 2), dtype=torch.float32, device=self.device)
-        T.check(lib().ttnn_rollout(self.net, _ptr(init_dev), _ptr(cond_dev), B, n_steps, _ptr(out)))
+        T.check(lib().ttnn_rollout(self.net, _ptr(init_dev), _ptr(cond_dev), _opt(prop_dev), B, n_steps, _ptr(out)))
         return out
 
     def ttnn_judge(self, pred_dev, ref_dev, tol):

@@ -23,6 +23,7 @@ TTNS_ENUMERIC = -4
 TTNS_FP64, TTNS_FP32, TTNS_BF16X3 = 0, 1, 2
 TTNS_EXEC_AUTO, TTNS_EXEC_WIDE, TTNS_EXEC_PERSISTENT = 0, 1, 2
 TTNS_FLAG_MFMA_ALL = 1
+TTNS_FLAG_AUTOTUNE = 2
 
 OBS_RDM, OBS_POP, OBS_LOCAL, OBS_NORM, OBS_ENERGY = 0, 1, 2, 3, 4
 OBS_HISTORY, OBS_RECORD_SIZE, OBS_TENSOR, OBS_STATS, OBS_BOND_DIMS = 5, 6, 7, 8, 9
@@ -31,7 +32,8 @@ OBS_STEP_FLOPS = 10
 EXPORTED = [
     "ttns_default_opts", "ttns_ohmic_chain", "ttns_workspace_size", "ttns_star_workspace_size",
     "ttns_build", "ttns_star_build", "ttns_apply_heff", "ttns_tdvp_step", "ttns_observe",
-    "ttns_profile", "ttns_profile_read", "ttns_profile_kernel", "ttns_destroy", "ttns_last_error",
+    "ttns_profile", "ttns_profile_read", "ttns_profile_kernel", "ttns_tuning_report", "ttns_destroy",
+    "ttns_last_error",
 ]
 # kernel ids (include/ttns.h) -> device symbol
 KERNELS = {0: "ttns::k_op<0> (scalar apply)", 1: "ttns::k_op<1> (scalar H_eff + Lanczos dots)",
@@ -109,6 +111,7 @@ def lib():
         L.ttns_profile.argtypes = [P, I]
         L.ttns_profile_read.argtypes = [P, I, C.POINTER(D), C.POINTER(C.c_int64), C.POINTER(D)]
         L.ttns_profile_kernel.argtypes = [P, I, C.POINTER(D), C.POINTER(C.c_int64), C.POINTER(D), C.POINTER(D)]
+        L.ttns_tuning_report.argtypes = [P, C.c_char_p, S, C.POINTER(S)]
         L.ttns_destroy.argtypes = [P]
         L.ttns_last_error.argtypes = []
         L.ttns_last_error.restype = C.c_char_p
@@ -317,6 +320,15 @@ class Context:
 
     def bond_dims(self, tree, n_nodes):
         return self.ttns_observe(OBS_BOND_DIMS, tree, n=n_nodes).astype(int)
+
+    def tuning_report(self):
+        """The autotuner's measurements and choices (empty without
+        TTNS_FLAG_AUTOTUNE)."""
+        need = C.c_size_t()
+        check(lib().ttns_tuning_report(self.ctx, None, 0, C.byref(need)))
+        buf = C.create_string_buffer(need.value)
+        check(lib().ttns_tuning_report(self.ctx, buf, need.value, None))
+        return buf.value.decode()
 
     def profile(self, enable=True):
         check(lib().ttns_profile(self.ctx, 1 if enable else 0))

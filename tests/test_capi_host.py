@@ -124,3 +124,17 @@ def test_rejects_bad_options():
     assert _build_status(t, krylov_dim=0) == T.TTNS_EINVAL
     assert _build_status(t, krylov_dim=17) == T.TTNS_EINVAL
     assert _build_status(t, record_capacity=0) == T.TTNS_EINVAL
+    assert _build_status(t, flags=4) == T.TTNS_EINVAL
+    assert b"flags" in T.lib().ttns_last_error()
+
+
+@pytest.mark.parametrize("model", [W.vibronic_reference(), W.large_tree(), W.vibronic_small()],
+                         ids=["vibronic", "large_er", "vibronic_small"])
+def test_autotune_probe_plan_bounds_the_workspace(model):
+    """With TTNS_FLAG_AUTOTUNE the size query plans every candidate (the
+    probe build); any final plan the autotuner picks needs no more."""
+    rc0, plain = _ws_size([model], record_capacity=2)
+    rc1, tuned = _ws_size([model], record_capacity=2, flags=T.TTNS_FLAG_AUTOTUNE)
+    rc2, all_mfma = _ws_size([model], record_capacity=2, flags=T.TTNS_FLAG_MFMA_ALL)
+    assert rc0 == rc1 == rc2 == T.TTNS_OK
+    assert tuned >= plain and tuned >= all_mfma

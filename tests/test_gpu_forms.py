@@ -82,3 +82,44 @@ def test_reduced_precision_trajectory_population_error(precision):
     assert pop <= 1e-5, pop
     # the FP64 parts still conserve the norm to round-off of the reduced products
     assert np.abs(hg["norm"] - 1).max() <= 1e-5
+
+
+def test_large_er_tree_full_size():
+    """The large tree at its full size (5-level root, 6 ER nodes, 8 chains x
+    100 sites, d = 30, D = 48), in the wide executor as the benchmark runs it:
+
+    * FP64 H_eff at sampled nodes (root, ER nodes, a chain head, a chain
+      site, a chain end) against the oracle at t = 0: 1e-12 relative;
+    * the split-BF16 form at the same nodes: 2e-5 relative;
+    * one TDVP step in both precisions: the split-BF16 populations within
+      1e-5 of the FP64 GPU run, FP64 norm and energy conserved to 1e-10.
+    """
+    import torch
+    T = _T()
+    m = W.large_tree()
+    tt = TTNS(build_tree(m))
+    nodes = [0, 1, 2, 3, 4, 102, 103]
+    rng = np.random.default_rng(13)
+    inputs = {v: rng.normal(size=tt.shape[v]) + 1j * rng.normal(size=tt.shape[v]) for v in nodes}
+    refs = {}
+    for v in nodes:
+        tt.move_to(v)
+        refs[v] = tt.apply_heff(v, inputs[v])
+    hist = {}
+    for prec, rel in ((0, 1e-12), (2, 2e-5)):
+        ctx = T.Context([m], opts=T.default_opts(record_capacity=3, precision=prec, executor=T.TTNS_EXEC_WIDE))
+        for v in nodes:
+            xd = torch.from_numpy(inputs[v].reshape(-1).copy()).to("cuda")
+            yd = torch.zeros_like(xd)
+            ctx.ttns_apply_heff(0, v, xd, yd)
+            got = yd.cpu().numpy().reshape(tt.shape[v])
+            err = np.abs(got - refs[v]).max() / np.abs(refs[v]).max()
+            assert err <= rel, (prec, v, err)
+        ctx.ttns_tdvp_step(m["dt"], 1)
+        hist[prec] = ctx.history()
+        ctx.close()
+    h64, h16 = hist[0], hist[2]
+    assert np.abs(h64["norm"] - 1).max() <= 1e-10
+    assert np.abs(h64["energy"] - h64["energy"][0]).max() <= 1e-10 * max(1.0, abs(h64["energy"][0]))
+    pop = np.abs(np.einsum("kjj->kj", h16["rdm"]).real - np.einsum("kjj->kj", h64["rdm"]).real).max()
+    assert pop <= 1e-5, pop

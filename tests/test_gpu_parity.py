@@ -79,6 +79,24 @@ def test_five_level_reference_size_first_steps():
     assert np.abs(hg["energy"] - hg["energy"][0]).max() < 1e-9
 
 
+@pytest.mark.parametrize("topology", ["star", "er"])
+def test_autotuned_build_matches_oracle(topology):
+    """The autotuner's probe build times every H_eff and tall-QR candidate;
+    the tuned plan must still reproduce the oracle's trajectory."""
+    T = _T()
+    m = dict(W.vibronic_small(steps=6, L=4, d=6, D=6), topology=topology)
+    ctx = T.Context([m], opts=T.default_opts(record_capacity=m["steps"] + 1, executor=T.TTNS_EXEC_WIDE,
+                                             flags=T.TTNS_FLAG_AUTOTUNE))
+    rep = ctx.tuning_report()
+    print(rep)
+    assert rep.count("->") >= 2 and "scalar" in rep
+    ctx.ttns_tdvp_step(m["dt"], m["steps"])
+    hg = ctx.history()
+    ctx.close()
+    _, ho = run(m)
+    assert_parity(hg, ho)
+
+
 def test_er_tree_eight_chains_small():
     m = W.vibronic(seed=4, n_chains=8, L=3, d=4, D=6, steps=4, topology="er", er_D=6)
     (hg,), _ = gpu_history([m], m["steps"])

@@ -13,11 +13,12 @@ from paper_1710_01362_amd import ttnn as N
 from paper_1710_01362_amd import ttns as T
 
 
+@pytest.mark.parametrize("skip", [0, 1])
 @pytest.mark.parametrize("n,window,nc,hidden,layers", [(5, 40, 39, 512, 3), (2, 3, 0, 7, 1), (3, 4, 5, 16, 2)])
-def test_param_count_matches_oracle_layout(n, window, nc, hidden, layers):
-    cfg = N.config(n, window, nc, hidden, layers, 64)
-    sizes = OL.layer_sizes(window, n * n, nc, hidden, layers)
-    params = OL.init_params(sizes, np.random.default_rng(0))
+def test_param_count_matches_oracle_layout(n, window, nc, hidden, layers, skip):
+    cfg = N.config(n, window, nc, hidden, layers, 64, skip)
+    sizes = OL.layer_sizes(window, n * n, nc, hidden, layers, bool(skip))
+    params = OL.init_params(sizes, np.random.default_rng(0), bool(skip))
     assert N.param_count(cfg) == OL.flatten(params).size
     assert N.workspace_size(cfg) >= 4 * (4 * N.param_count(cfg) + 64 * (window * n * n + nc))
 
@@ -32,7 +33,8 @@ def test_conditioning_matches_oracle():
 
 
 @pytest.mark.parametrize("bad", [dict(n_levels=0), dict(n_levels=9), dict(window=0), dict(hidden=0),
-                                 dict(layers=0), dict(layers=9), dict(max_batch=0), dict(n_cond=-1)])
+                                 dict(layers=0), dict(layers=9), dict(max_batch=0), dict(n_cond=-1),
+                                 dict(skip=2)])
 def test_bad_configs_rejected(bad):
     kw = dict(n_levels=5, window=4, n_cond=3, hidden=8, layers=2, max_batch=4)
     kw.update(bad)
@@ -48,3 +50,15 @@ def test_conditioning_output_too_small():
     out = np.zeros(38, dtype=np.float32)
     n = C.c_int32()
     assert N.lib().ttnn_conditioning(C.byref(sm), out.ctypes.data, 38, C.byref(n)) == T.TTNS_EINVAL
+
+
+def test_free_propagator_matches_oracle():
+    """exp(-i H_S dt) of the library (host FP64, rounded to FP32) against
+    the oracle's scipy expm, for the five-level family and a spin."""
+    for m, dt in ((W.vibronic_reference(), W.vibronic_reference()["dt"]), (W.spin_boson_reference(), 0.05),
+                  (W.vibronic(seed=11, n_levels=3), 7.3)):
+        got = N.propagator(m, dt)
+        n = int(np.asarray(m["h_el"]).shape[0])
+        U = got[0::2].reshape(n, n) + 1j * got[1::2].reshape(n, n)
+        ref = OL.propagator(m, dt)
+        assert np.abs(U - ref).max() <= 2e-7

@@ -89,3 +89,94 @@ def test_trace_distance_of_pure_states():
         b /= np.linalg.norm(b)
         t = LR.trace_distance(np.outer(a, a.conj()), np.outer(b, b.conj()))
         assert abs(t - np.sqrt(1 - abs(np.vdot(a, b)) ** 2)) < 1e-12
+
+
+def test_gradients_with_propagated_residual_match_central_differences():
+    params, X, Y, ne, window, sizes = _tiny()
+    rng = np.random.default_rng(5)
+    R = rng.normal(size=Y.shape)
+    loss, grads = LR.loss_and_grads(params, X, Y, ne, window, R)
+    flat, gflat = LR.flatten(params), LR.flatten(grads)
+    for i in rng.choice(flat.size, 20, replace=False):
+        h = 1e-6
+        fp, fm = flat.copy(), flat.copy()
+        fp[i] += h
+        fm[i] -= h
+        lp, _ = LR.loss_and_grads(LR.unflatten(fp, sizes), X, Y, ne, window, R)
+        lm, _ = LR.loss_and_grads(LR.unflatten(fm, sizes), X, Y, ne, window, R)
+        assert abs((lp - lm) / (2 * h) - gflat[i]) <= 1e-8 + 1e-6 * abs(gflat[i])
+
+
+def test_free_propagation_closed_form():
+    """Diagonal H_S: rho_jk picks up exp(-i (E_j - E_k) dt); the trace and
+    the spectrum are kept; U = 1 leaves rho unchanged."""
+    rng = np.random.default_rng(6)
+    n, dt = 5, 0.7
+    E = rng.uniform(0, 0.3, n)
+    U = LR.propagator({"h_el": np.diag(E)}, dt)
+    rho = _rand_rho(rng, n, 4)
+    got = LR.decode(LR.propagate(LR.encode(rho), U, n), n)
+    ph = np.exp(-1j * (E[:, None] - E[None, :]) * dt)
+    np.testing.assert_allclose(got, rho * ph, atol=1e-14)
+    H = rng.normal(size=(n, n))
+    U2 = LR.propagator({"h_el": (H + H.T) / 2}, dt)
+    got2 = LR.decode(LR.propagate(LR.encode(rho), U2, n), n)
+    np.testing.assert_allclose(np.trace(got2, axis1=1, axis2=2), 1.0, atol=1e-14)
+    np.testing.assert_allclose(np.linalg.eigvalsh(got2), np.linalg.eigvalsh(rho), atol=1e-13)
+    np.testing.assert_allclose(LR.propagate(LR.encode(rho), np.eye(n), n), LR.encode(rho), atol=1e-15)
+
+
+def test_rollout_with_zero_network_is_free_propagation():
+    rng = np.random.default_rng(7)
+    n, window = 5, 3
+    sizes = LR.layer_sizes(window, 25, 4, 6, 2)
+    params = LR.init_params(sizes, rng)
+    params[-1] = (np.zeros_like(params[-1][0]), np.zeros_like(params[-1][1]))
+    H = rng.normal(size=(n, n))
+    U = LR.propagator({"h_el": (H + H.T) / 2}, 0.3)
+    rho = _rand_rho(rng, n, 2)
+    init = np.repeat(LR.encode(rho)[:, None, :], window, axis=1)
+    out = LR.rollout(params, init, rng.normal(size=(2, 4)), 4, n, window, np.stack([U, U]))
+    ref = rho
+    for k in range(4):
+        ref = U @ ref @ np.conj(U.T)
+        np.testing.assert_allclose(LR.decode(out[:, k], n), ref, atol=1e-13)
+
+
+def test_skip_network_gradients_match_central_differences():
+    rng = np.random.default_rng(9)
+    window, n, nc = 2, 2, 3
+    sizes = LR.layer_sizes(window, n * n, nc, 5, 2, skip=True)
+    params = LR.init_params(sizes, rng, skip=True)
+    params[-1] = (rng.normal(size=params[-1][0].shape) * 0.1, None)
+    traj = rng.normal(size=(3, 6, n * n))
+    cond = rng.normal(size=(3, nc))
+    smp = np.array([[0, 2], [1, 3], [2, 4], [0, 1]])
+    X, Y, R = LR.windows(traj, cond, smp, window, skip=True)
+    assert X.shape[1] == sizes[0] == window * n * n + nc + nc * n * n
+    # the bilinear block is cond (x) the last RDM
+    np.testing.assert_allclose(X[1, window * n * n + nc:].reshape(nc, n * n), np.outer(cond[1], traj[1, 3]))
+    loss, grads = LR.loss_and_grads(params, X, Y, n * n, window, R)
+    flat, gflat = LR.flatten(params), LR.flatten(grads)
+    assert flat.size == gflat.size
+    for i in rng.choice(flat.size, 30, replace=False):
+        h = 1e-6
+        fp, fm = flat.copy(), flat.copy()
+        fp[i] += h
+        fm[i] -= h
+        lp, _ = LR.loss_and_grads(LR.unflatten(fp, sizes, True), X, Y, n * n, window, R)
+        lm, _ = LR.loss_and_grads(LR.unflatten(fm, sizes, True), X, Y, n * n, window, R)
+        assert abs((lp - lm) / (2 * h) - gflat[i]) <= 1e-8 + 1e-6 * abs(gflat[i])
+
+
+def test_skip_only_network_is_linear_in_the_input():
+    """Zero MLP output layer: the prediction is base + W_s x exactly."""
+    rng = np.random.default_rng(10)
+    sizes = LR.layer_sizes(2, 4, 3, 5, 2, skip=True)
+    params = LR.init_params(sizes, rng, skip=True)
+    params[-2] = (np.zeros_like(params[-2][0]), np.zeros_like(params[-2][1]))
+    Ws = rng.normal(size=params[-1][0].shape)
+    params[-1] = (Ws, None)
+    X = rng.normal(size=(5, sizes[0]))
+    pred, _ = LR.forward(params, X, 4, 2)
+    np.testing.assert_allclose(pred, X[:, 4:8] + X @ Ws.T, atol=1e-13)
