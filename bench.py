@@ -103,6 +103,7 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--executor", default="auto", choices=["auto", "wide", "persistent", "cooperative"])
     ap.add_argument("--autotune", action="store_true",
                     help="time the H_eff and QR variants at build and plan the fastest")
     args = ap.parse_args()
@@ -120,12 +121,14 @@ def main():
     total = args.warmup + args.steps + args.profile_steps + 1
     flags = T.TTNS_FLAG_AUTOTUNE if args.autotune else 0
     t_build = time.perf_counter()
-    ctx = T.Context(models, opts=T.default_opts(record_capacity=total + 1,
+    ex = {"auto": T.TTNS_EXEC_AUTO, "wide": T.TTNS_EXEC_WIDE, "persistent": T.TTNS_EXEC_PERSISTENT,
+          "cooperative": T.TTNS_EXEC_COOPERATIVE}[args.executor]
+    ctx = T.Context(models, opts=T.default_opts(record_capacity=total + 1, executor=ex,
                                                 precision=PREC[args.precision], flags=flags))
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t_build
     dt = models[0]["dt"]
-    persistent = len(models) > 1
+    persistent = args.executor == "persistent" or (args.executor == "auto" and len(models) > 1)
 
     ctx.ttns_tdvp_step(dt, args.warmup)
     torch.cuda.synchronize()
@@ -152,7 +155,9 @@ def main():
         "config": {"workload": desc, "trees": len(models), "site_updates_per_step": upd_per_step,
                    "krylov": models[0]["krylov"],
                    "executor": "one persistent workgroup per tree" if persistent
-                   else "one kernel per operation, replayed as a HIP graph",
+                   else ("all workgroups per operation, grid barriers, one cooperative launch per stretch"
+                         if args.executor == "cooperative"
+                         else "one kernel per operation, replayed as a HIP graph"),
                    "autotuned": bool(args.autotune), "build_s": round(t_build, 2)},
         "step_tflops": step_flops / (el / args.steps) / 1e12,
     }

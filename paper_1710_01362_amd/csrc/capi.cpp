@@ -215,6 +215,15 @@ struct ttns_ctx {
   std::vector<hipGraph_t> graphs;
   std::vector<hipGraphExec_t> gexecs;
   bool persistent = false;
+  bool coop = false;               // cooperative executor
+  int coop_blocks = 0;             // its grid size
+  size_t o_bar = 0;                // its GridBar
+  GridBar* d_bar = nullptr;
+  struct Launch {
+    int begin, end;  // a cooperative stretch of the step program, or
+    int single;      // >= 0: one op launched on its own (matrix-core groups)
+  };
+  std::vector<Launch> coop_plan;
   bool profile = false;
   double prof_ms = 0.0, prof_flops = 0.0;
   int64_t prof_n = 0;
@@ -1309,10 +1318,11 @@ int prepare(ttns_ctx& c, std::vector<TreeState>&& trees, const ttns_opts* opts, 
   if (o.record_capacity < 1) return fail(TTNS_EINVAL, "record_capacity must be >= 1");
   if (!(o.rank_tol > 0) || !(o.breakdown_tol > 0)) return fail(TTNS_EINVAL, "tolerances must be > 0");
   if (o.precision < TTNS_FP64 || o.precision > TTNS_BF16X3) return fail(TTNS_EINVAL, "bad precision");
-  if (o.executor < TTNS_EXEC_AUTO || o.executor > TTNS_EXEC_PERSISTENT) return fail(TTNS_EINVAL, "bad executor");
+  if (o.executor < TTNS_EXEC_AUTO || o.executor > TTNS_EXEC_COOPERATIVE) return fail(TTNS_EINVAL, "bad executor");
   if (o.flags & ~(TTNS_FLAG_MFMA_ALL | TTNS_FLAG_AUTOTUNE)) return fail(TTNS_EINVAL, "unknown option flags");
   c.opts = o;
   c.trees = std::move(trees);
+  c.coop = o.executor == TTNS_EXEC_COOPERATIVE;
   c.persistent = (o.executor == TTNS_EXEC_PERSISTENT) ||
                  (o.executor == TTNS_EXEC_AUTO && c.trees.size() > 1);
   for (auto& t : c.trees) {
@@ -1419,8 +1429,9 @@ int prepare(ttns_ctx& c, std::vector<TreeState>&& trees, const ttns_opts* opts, 
   c.o_modes = take(c.modes.size() * sizeof(ModeDesc));
   c.o_bonds = take(c.bonds.size() * sizeof(BondDesc));
   c.o_trees = take(c.trees.size() * sizeof(TreeDev));
-  // the op table is read only by the persistent executor
-  c.o_prog = take(c.persistent ? persistent_prog.size() * sizeof(Op) : 0);
+  // the op table is read by the persistent and cooperative executors
+  c.o_prog = take((c.persistent || c.coop) ? persistent_prog.size() * sizeof(Op) : 0);
+  c.o_bar = take(sizeof(GridBar));
   c.o_begin = take(c.trees.size() * sizeof(int));
   c.o_end = take(c.trees.size() * sizeof(int));
   c.total = align256(off);
@@ -1443,6 +1454,7 @@ int prepare(ttns_ctx& c, std::vector<TreeState>&& trees, const ttns_opts* opts, 
   c.tables.bonds = (const BondDesc*)(c.ws + c.o_bonds);
   c.tables.trees = (const TreeDev*)(c.ws + c.o_trees);
   c.d_ops = (Op*)(c.ws + c.o_prog);
+  c.d_bar = (GridBar*)(c.ws + c.o_bar);
   c.d_begin = (int*)(c.ws + c.o_begin);
   c.d_end = (int*)(c.ws + c.o_end);
   // zero the workspace once (environments, scalars, counters, records)
@@ -1470,8 +1482,23 @@ int prepare(ttns_ctx& c, std::vector<TreeState>&& trees, const ttns_opts* opts, 
   if ((rc = upload(c, c.o_modes, c.modes.data(), c.modes.size() * sizeof(ModeDesc)))) return rc;
   if ((rc = upload(c, c.o_bonds, c.bonds.data(), c.bonds.size() * sizeof(BondDesc)))) return rc;
   if ((rc = upload(c, c.o_trees, tdev.data(), tdev.size() * sizeof(TreeDev)))) return rc;
-  if (c.persistent)
+  if (c.persistent || c.coop)
     if ((rc = upload(c, c.o_prog, persistent_prog.data(), persistent_prog.size() * sizeof(Op)))) return rc;
+  if (c.coop) {
+    // stretches between matrix-core launches
+    c.coop_plan.clear();
+    int start = 0;
+    for (int i = 0; i <= (int)persistent_prog.size(); ++i) {
+      const bool single = i < (int)persistent_prog.size() && persistent_prog[i].type == OP_MODE;
+      if (i == (int)persistent_prog.size() || single) {
+        if (i > start) c.coop_plan.push_back({start, i, -1});
+        if (single) c.coop_plan.push_back({0, 0, i});
+        start = i + 1;
+      }
+    }
+    c.coop_blocks = coop_max_blocks();
+    if (c.coop_blocks < 1) return fail(TTNS_EDEVICE, "cooperative launch not available on this device");
+  }
   if ((rc = upload(c, c.o_begin, c.tree_begin.data(), c.tree_begin.size() * sizeof(int)))) return rc;
   if ((rc = upload(c, c.o_end, c.tree_end.data(), c.tree_end.size() * sizeof(int)))) return rc;
   if ((rc = set_half(c, 0.0))) return rc;
@@ -1979,6 +2006,14 @@ int ttns_tdvp_step(ttns_ctx* c, double dt, int32_t n_steps) {
       if ((rc = run_ops(*c, c->step_ops))) return rc;
     return TTNS_OK;
   }
+  if (c->coop) {
+    for (int s = 0; s < n_steps; ++s)
+      for (const auto& L : c->coop_plan) {
+        if (L.single >= 0) HIPCHK(launch_op(c->step_ops[L.single], c->tables, c->stream));
+        else HIPCHK(launch_coop(c->d_ops, L.begin, L.end, c->tables, c->d_bar, c->coop_blocks, c->stream));
+      }
+    return TTNS_OK;
+  }
   if ((rc = build_graph(*c))) return rc;
   for (int s = 0; s < n_steps; ++s)
     for (auto ge : c->gexecs) HIPCHK(hipGraphLaunch(ge, c->stream));
@@ -1988,6 +2023,12 @@ int ttns_tdvp_step(ttns_ctx* c, double dt, int32_t n_steps) {
 int ttns_observe(ttns_ctx* c, int32_t kind, int32_t tree, int32_t index, double* host_out, size_t n_out) {
   if (!c || tree < 0 || tree >= (int)c->trees.size() || !host_out)
     return fail(TTNS_EINVAL, "ttns_observe: bad arguments");
+  if (c->coop) {  // a timed-out grid barrier invalidates every later result
+    GridBar hb{};
+    HIPCHK(hipMemcpyAsync(&hb, c->d_bar, sizeof hb, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (hb.abort) return fail(TTNS_EDEVICE, "cooperative executor: a grid barrier timed out");
+  }
   TreeState& t = c->trees[tree];
   HIPCHK(hipStreamSynchronize(c->stream));
   int count = 0;

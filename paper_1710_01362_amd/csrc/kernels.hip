@@ -30,7 +30,7 @@ struct Smem {
     cd lanes[kBlock];                 // wide-QR fold helpers
   };
   cd fold[64];
-  int ival[4];
+  int ival[6];  // [4], [5]: the cooperative executor's barrier state
   double dval[4];
 };
 
@@ -504,8 +504,10 @@ __device__ void body_qr_t(const Op& op, const DevTables& T, Smem& sm, cd* lds) {
   const int cols = sh.dims[ax];
   const int rows = sh.size / cols;
   const int cst = sh.stride[ax];
-  cd* A = tr.qrA;
   cd* Q = kLds ? lds : tr.qrQ;
+  // with LDS, A is gathered into Q's own buffer: column k of A is read (into
+  // registers, one column ahead) before column k of Q overwrites it
+  cd* A = kLds ? lds : tr.qrA;
   cd* v = kLds ? lds + (size_t)rows * cols : tr.qrv;
   cd* u = kLds ? v + rows : tr.qrv + tr.max_rows;
   cd* R = tr.R;
@@ -1304,6 +1306,153 @@ hipError_t launch_op(const Op& op, const DevTables& t, hipStream_t s) {
       return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+// ------------------------------------------------------------ cooperative executor
+// Every resident workgroup runs the same stretch of a step program: the
+// virtual workgroups of each op are dealt out round-robin, a grid barrier
+// separates consecutive ops, and the fold of a reduction op runs in
+// workgroup 0 between two barriers.  One-workgroup ops (QR, bond step,
+// record) run in workgroup 0 while the others wait at the barrier.
+//
+// The barrier: each workgroup adds to `count`; the last one resets it and
+// advances `gen`, which the others poll.  Waits are bounded: after
+// kSpinLimit polls a workgroup raises `abort`, and every later barrier lets
+// all workgroups through at once, so the launch always ends (the host then
+// reports the step as failed).
+constexpr long kSpinLimit = 1l << 22;
+
+__device__ bool grid_sync(GridBar* bar, unsigned& gen, Smem& sm) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned target = gen + 1u;
+    const unsigned prev = atomicAdd(&bar->count, 1u);
+    if (prev == gridDim.x - 1u) {
+      atomicExch(&bar->count, 0u);
+      __threadfence();
+      atomicExch(&bar->gen, target);
+    } else {
+      // relaxed polls (an acquire per poll would invalidate the L2 the
+      // working workgroups use); one acquire fence once the wait is over
+      long spins = 0;
+      while (__hip_atomic_load(&bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != target) {
+        if (__hip_atomic_load(&bar->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+        if (++spins > kSpinLimit) {
+          atomicExch(&bar->abort, 1);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    sm.ival[4] = __hip_atomic_load(&bar->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+  }
+  __syncthreads();
+  gen += 1u;
+  return sm.ival[4] == 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_coop(const Op* __restrict__ ops, int begin, int end, DevTables T,
+                                                 GridBar* bar) {
+  __shared__ Smem sm;
+  __shared__ cd qr_lds[kQrLds];
+  const int b = blockIdx.x, G = gridDim.x;
+  if (threadIdx.x == 0) sm.ival[5] = (int)__hip_atomic_load(&bar->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  unsigned gen = (unsigned)sm.ival[5];
+  __syncthreads();
+  for (int i = begin; i < end; ++i) {
+    const Op op = ops[i];
+    const int nvb = op.nvb;
+    switch (op.type) {
+      case OP_APPLY:
+        for (int vb = b; vb < nvb; vb += G) body_apply(op, T, vb);
+        break;
+      case OP_APPLY_LZ: {
+        bool act = true;  // uniform: workgroup 0 always holds virtual workgroup 0
+        for (int vb = b; vb < nvb && act; vb += G) act = body_apply_lz(op, T, vb, sm);
+        grid_sync(bar, gen, sm);
+        if (b == 0 && act) fin_apply_lz(op, T, nvb, sm);
+        break;
+      }
+      case OP_NORM:
+        for (int vb = b; vb < nvb; vb += G) body_norm(op, T, vb, sm);
+        grid_sync(bar, gen, sm);
+        if (b == 0) fin_norm(op, T, nvb, sm);
+        break;
+      case OP_SCALE:
+        for (int vb = b; vb < nvb; vb += G) body_scale(op, T, vb);
+        break;
+      case OP_ORTH1: {
+        bool act = true;
+        for (int vb = b; vb < nvb && act; vb += G) act = body_orth1(op, T, vb, sm);
+        grid_sync(bar, gen, sm);
+        if (b == 0 && act) fin_orth1(op, T, nvb, sm);
+        break;
+      }
+      case OP_ORTH2: {
+        bool act = true;
+        for (int vb = b; vb < nvb && act; vb += G) act = body_orth2(op, T, vb);
+        grid_sync(bar, gen, sm);
+        if (b == 0 && act) fin_orth2(op, T);
+        break;
+      }
+      case OP_COMBINE:
+        for (int vb = b; vb < nvb; vb += G) body_combine(op, T, vb, sm);
+        break;
+      case OP_QR:
+        if (b == 0) body_qr(op, T, sm, qr_lds);
+        break;
+      case OP_CONTRACT:
+        for (int vb = b; vb < nvb; vb += G) body_contract(op, T, vb, sm, qr_lds);
+        grid_sync(bar, gen, sm);
+        if (b == 0) fin_contract(op, T, nvb);
+        break;
+      case OP_BOND:
+        if (b == 0) body_bond(op, T, sm, qr_lds);
+        break;
+      case OP_QRW: {
+        bool act = false;
+        for (int vb = b; vb < nvb; vb += G) act = body_qrw(op, T, vb, sm) || act;
+        // workgroup 0 holds virtual workgroup 0, whose answer is the op's
+        grid_sync(bar, gen, sm);
+        if (b == 0 && act) fin_qrw(op, T, nvb, sm);
+        break;
+      }
+      case OP_COPY:
+        for (int vb = b; vb < nvb; vb += G) body_copy(op, vb);
+        break;
+      case OP_DOT:
+        for (int vb = b; vb < nvb; vb += G) body_dot(op, T, vb, sm);
+        grid_sync(bar, gen, sm);
+        if (b == 0) fin_dot(op, T, nvb, sm);
+        break;
+      case OP_RECORD:
+        if (b == 0) body_record(op, T);
+        break;
+      case OP_SETH:
+        if (b == 0 && threadIdx.x == 0) *T.half_step = op.d0;
+        break;
+      default:
+        break;
+    }
+    grid_sync(bar, gen, sm);
+  }
+}
+
+int coop_max_blocks() {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_coop, kBlock, 0) != hipSuccess) return 0;
+  return cus * per;
+}
+
+hipError_t launch_coop(const Op* dev_ops, int begin, int end, const DevTables& t, GridBar* bar, int blocks,
+                       hipStream_t s) {
+  void* args[] = {(void*)&dev_ops, (void*)&begin, (void*)&end, (void*)&t, (void*)&bar};
+  return hipLaunchCooperativeKernel((const void*)k_coop, dim3(blocks), dim3(kBlock), args, 0, s);
 }
 
 hipError_t launch_persistent(const Op* dev_ops, const int* dev_begin, const int* dev_end,

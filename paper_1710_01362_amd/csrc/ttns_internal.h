@@ -226,6 +226,16 @@ hipError_t launch_persistent(const Op* dev_ops, const int* dev_begin,
                              const int* dev_end, int n_trees,
                              const DevTables& t, hipStream_t s);
 hipError_t launch_set_half_step(double* dst, double h, hipStream_t s);
+
+// Grid barrier state of the cooperative executor (in the workspace, zeroed).
+struct GridBar {
+  unsigned count, gen;
+  int abort, pad;
+};
+// resident workgroups of the cooperative kernel on the current device
+int coop_max_blocks();
+hipError_t launch_coop(const Op* dev_ops, int begin, int end, const DevTables& t, GridBar* bar, int blocks,
+                       hipStream_t s);
 // MFMA limits: bond dimension per precision, columns per workgroup tile
 constexpr int kModeNT = 64;
 int mode_max_bond(int prec);

@@ -21,7 +21,7 @@ TTNS_EDEVICE = -3
 TTNS_ENUMERIC = -4
 
 TTNS_FP64, TTNS_FP32, TTNS_BF16X3 = 0, 1, 2
-TTNS_EXEC_AUTO, TTNS_EXEC_WIDE, TTNS_EXEC_PERSISTENT = 0, 1, 2
+TTNS_EXEC_AUTO, TTNS_EXEC_WIDE, TTNS_EXEC_PERSISTENT, TTNS_EXEC_COOPERATIVE = 0, 1, 2, 3
 TTNS_FLAG_MFMA_ALL = 1
 TTNS_FLAG_AUTOTUNE = 2
 

@@ -97,6 +97,29 @@ def test_autotuned_build_matches_oracle(topology):
     assert_parity(hg, ho)
 
 
+@pytest.mark.parametrize("topology", ["star", "er"])
+def test_cooperative_executor_matches_oracle(topology):
+    """All resident workgroups run the step program with grid barriers."""
+    T = _T()
+    m = dict(W.vibronic_small(steps=8), topology=topology)
+    (hg,), (st,) = gpu_history([m], m["steps"], executor=T.TTNS_EXEC_COOPERATIVE)
+    _, ho = run(m)
+    assert_parity(hg, ho)
+    assert st["steps"] == m["steps"]
+
+
+def test_cooperative_executor_equals_wide_at_full_size():
+    """Five-level tree at full size, the root on the matrix cores between the
+    cooperative stretches: the same FP64 results as the wide executor (the
+    same partial sums folded in the same order)."""
+    T = _T()
+    m = W.vibronic_reference()
+    (hw,), _ = gpu_history([m], 2, executor=T.TTNS_EXEC_WIDE)
+    (hc,), _ = gpu_history([m], 2, executor=T.TTNS_EXEC_COOPERATIVE)
+    assert np.abs(hw["rdm"] - hc["rdm"]).max() <= 1e-12
+    assert np.abs(hw["energy"] - hc["energy"]).max() <= 1e-12 * max(1.0, np.abs(hw["energy"]).max())
+
+
 def test_er_tree_eight_chains_small():
     m = W.vibronic(seed=4, n_chains=8, L=3, d=4, D=6, steps=4, topology="er", er_D=6)
     (hg,), _ = gpu_history([m], m["steps"])
