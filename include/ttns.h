@@ -56,10 +56,13 @@ extern "C" {
 #define TTNS_EXEC_AUTO 0
 #define TTNS_EXEC_WIDE 1       /* each operation spread over many workgroups */
 #define TTNS_EXEC_PERSISTENT 2 /* one workgroup runs a whole tree's step     */
-#define TTNS_EXEC_COOPERATIVE 3 /* all resident workgroups run the step
+#define TTNS_EXEC_COOPERATIVE 3 /* 32 co-resident workgroups run the step
                                    program together, a grid barrier between
                                    operations, one cooperative launch per
-                                   stretch between matrix-core launches    */
+                                   stretch between matrix-core launches
+                                   (slower than TTNS_EXEC_WIDE on MI355X:
+                                   a grid barrier costs more than a kernel
+                                   boundary in a replayed graph)           */
 
 /* option flags */
 #define TTNS_FLAG_MFMA_ALL 1u  /* matrix-core H_eff for every node whose bonds

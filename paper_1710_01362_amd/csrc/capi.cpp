@@ -40,6 +40,7 @@ constexpr int kMaxContractVb = 64;
 constexpr int kMfmaMinSize = 16384;  // nodes this large use the matrix cores
 constexpr size_t kGraphSegment = 8192;  // launches per captured graph
 constexpr int kQrOneGroupRows = 4096;   // tallest QR left to one workgroup
+constexpr int kCoopBlocks = 32;         // grid of the cooperative executor
 
 // Channel of an environment: the block Hamiltonian (kind 0), one end of a
 // two-node term (kind 1: term k, end 0 = node_a / 1 = node_b) or a recorded
@@ -1496,7 +1497,10 @@ int prepare(ttns_ctx& c, std::vector<TreeState>&& trees, const ttns_opts* opts, 
         start = i + 1;
       }
     }
-    c.coop_blocks = coop_max_blocks();
+    // 32 workgroups measured best on the five-level tree (8: 814 ms/step,
+    // 32: 437, 96: 500, all resident: 746): the barrier's cost grows with
+    // the number of arriving workgroups faster than the ops shrink
+    c.coop_blocks = std::min(coop_max_blocks(), kCoopBlocks);
     if (c.coop_blocks < 1) return fail(TTNS_EDEVICE, "cooperative launch not available on this device");
   }
   if ((rc = upload(c, c.o_begin, c.tree_begin.data(), c.tree_begin.size() * sizeof(int)))) return rc;

@@ -58,12 +58,15 @@ __device__ double wave_max(double v) {
 }
 
 // Atomic ticket: true in the workgroup that finishes last (wide executor).
-// Every thread releases its own writes before the barrier; the winner
+// Each workgroup releases its writes before taking a ticket; the winner
 // acquires before it reads the other workgroups' partial results.
 __device__ bool last_block(unsigned* counter, int nvb, Smem& sm) {
-  __threadfence();
+  // the workgroup barrier completes every wave's stores to this CU's L2
+  // path; one agent-scope release by thread 0 then publishes them all
+  // (cumulative over the barrier), instead of one L2 writeback per wave
   __syncthreads();
   if (threadIdx.x == 0) {
+    __threadfence();
     const unsigned prev = atomicAdd(counter, 1u);
     sm.ival[0] = (prev == (unsigned)(nvb - 1));
     if (sm.ival[0]) atomicExch(counter, 0u);
@@ -1323,9 +1326,9 @@ hipError_t launch_op(const Op& op, const DevTables& t, hipStream_t s) {
 constexpr long kSpinLimit = 1l << 22;
 
 __device__ bool grid_sync(GridBar* bar, unsigned& gen, Smem& sm) {
-  __threadfence();
-  __syncthreads();
+  __syncthreads();  // as in last_block: one release per workgroup
   if (threadIdx.x == 0) {
+    __threadfence();
     const unsigned target = gen + 1u;
     const unsigned prev = atomicAdd(&bar->count, 1u);
     if (prev == gridDim.x - 1u) {
