@@ -93,6 +93,15 @@ extern "C" {
 #define TTNS_OBS_BOND_DIMS 9 /* clamped bond dims, n_nodes doubles (0: root) */
 #define TTNS_OBS_STEP_FLOPS 10 /* algorithmic real flops of one step of this
                                   tree: [total, H_eff contractions only]     */
+#define TTNS_OBS_ENTROPY 11  /* von Neumann entropy -sum p ln p of the
+                                Schmidt values across the bond between node
+                                `index` (not the root) and its parent, i.e.
+                                of the bipartition (subtree of index | rest),
+                                1 double, from the current state (TTNS
+                                section: S = -Tr rho ln rho of a bond).  It
+                                moves the centre to the parent of `index`
+                                (gauge only; the next ttns_tdvp_step returns
+                                it to the root)                              */
 
 typedef struct {
   double re, im;

@@ -493,6 +493,19 @@ class TTNS:
         C = self.T[0]
         return complex(np.vdot(C, mode_product(M, C, self.axis_of(0, v))))
 
+    def bond_entropy(self, v):
+        """Von Neumann entropy of the bipartition (subtree of v | rest):
+        with the centre moved to v, the Schmidt values across v's parent bond
+        are the singular values of C_v matricised towards the parent axis
+        (everything outside is an isometry in the parent index, everything
+        below in v's other legs).  Leaves the centre at v."""
+        assert v != 0
+        self.move_to(v)
+        s = np.linalg.svd(matricize(self.T[v], self.axis_of(v, self.parent[v])), compute_uv=False)
+        p = s ** 2 / np.sum(s ** 2)
+        p = p[p > 1e-300]
+        return float(-np.sum(p * np.log(p)))
+
     def full_state(self):
         """Contract the tree into the full state vector (tiny trees only);
         the index order is the node order, physical legs only."""

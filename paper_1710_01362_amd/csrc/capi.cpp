@@ -1732,6 +1732,68 @@ namespace ttns {
 int set_error(int code, const std::string& msg) { return fail(code, msg); }
 }  // namespace ttns
 
+namespace {
+// -sum p ln p over p = sigma^2 / sum sigma^2, sigma the singular values of
+// the D x D complex R (row-major): eigenvalues of R^H R from cyclic Jacobi
+// rotations of its real symmetric 2D x 2D embedding [[X, -Y], [Y, X]]
+// (every eigenvalue twice).
+double schmidt_entropy(const std::vector<cd>& R, int D) {
+  const int N = 2 * D;
+  std::vector<double> A((size_t)N * N, 0.0);
+  for (int i = 0; i < D; ++i)
+    for (int j = 0; j < D; ++j) {
+      double x = 0.0, y = 0.0;  // (R^H R)_ij = sum_k conj(R_ki) R_kj
+      for (int k = 0; k < D; ++k) {
+        const cd a = R[(size_t)k * D + i], b = R[(size_t)k * D + j];
+        x += a.x * b.x + a.y * b.y;
+        y += a.x * b.y - a.y * b.x;
+      }
+      A[(size_t)i * N + j] = x;
+      A[(size_t)(D + i) * N + D + j] = x;
+      A[(size_t)(D + i) * N + j] = y;
+      A[(size_t)i * N + D + j] = -y;
+    }
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int p = 0; p < N; ++p)
+      for (int q = 0; q < N; ++q) {
+        tot += A[(size_t)p * N + q] * A[(size_t)p * N + q];
+        if (p != q) off += A[(size_t)p * N + q] * A[(size_t)p * N + q];
+      }
+    if (off <= 1e-30 * tot) break;
+    for (int p = 0; p < N; ++p)
+      for (int q = p + 1; q < N; ++q) {
+        const double apq = A[(size_t)p * N + q];
+        if (std::fabs(apq) < 1e-300) continue;
+        const double th = (A[(size_t)q * N + q] - A[(size_t)p * N + p]) / (2.0 * apq);
+        const double tn = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double cs = 1.0 / std::sqrt(1.0 + tn * tn), sn = tn * cs;
+        for (int k = 0; k < N; ++k) {
+          const double x = A[(size_t)k * N + p], y = A[(size_t)k * N + q];
+          A[(size_t)k * N + p] = cs * x - sn * y;
+          A[(size_t)k * N + q] = sn * x + cs * y;
+        }
+        for (int k = 0; k < N; ++k) {
+          const double x = A[(size_t)p * N + k], y = A[(size_t)q * N + k];
+          A[(size_t)p * N + k] = cs * x - sn * y;
+          A[(size_t)q * N + k] = sn * x + cs * y;
+        }
+      }
+  }
+  // each eigenvalue lambda appears twice: with q = lambda / (2 sum lambda)
+  // over the 2D diagonal, p = 2 q and -sum p ln p = -sum_2D q ln q - ln 2
+  double sum = 0.0;
+  for (int i = 0; i < N; ++i) sum += std::max(A[(size_t)i * N + i], 0.0);
+  if (!(sum > 0.0)) return 0.0;
+  double S = 0.0;
+  for (int i = 0; i < N; ++i) {
+    const double q = std::max(A[(size_t)i * N + i], 0.0) / sum;
+    if (q > 1e-300) S -= q * std::log(q);
+  }
+  return std::max(S - std::log(2.0), 0.0);
+}
+}  // namespace
+
 // ====================================================================== C-ABI
 extern "C" {
 
@@ -2105,6 +2167,24 @@ int ttns_observe(ttns_ctx* c, int32_t kind, int32_t tree, int32_t index, double*
       if ((rc = need(t.n))) return rc;
       for (int v = 0; v < t.n; ++v) host_out[v] = t.D[v];
       return TTNS_OK;
+    case TTNS_OBS_ENTROPY: {
+      if (index < 1 || index >= t.n) return fail(TTNS_EINVAL, "ttns_observe: entropy needs a non-root node");
+      if ((rc = need(1))) return rc;
+      // centre to `index`, then the gauge move to its parent: the QR's R
+      // carries the Schmidt values of the bond
+      const int par = parent_of(t, index);
+      std::vector<Op> ops;
+      Builder b{*c, t, tree, ops};
+      b.move_to(index);
+      b.move(index, par, false);
+      if ((rc = validate_program(*c, ops, false)) || (rc = run_ops(*c, ops))) return rc;
+      const int D = t.shape[index].dims[axis_of(t, index, par)];
+      std::vector<cd> R((size_t)D * D);
+      HIPCHK(hipMemcpyAsync(R.data(), t.dev.R, R.size() * sizeof(cd), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+      host_out[0] = schmidt_entropy(R, D);
+      return TTNS_OK;
+    }
     default:
       return fail(TTNS_EINVAL, "ttns_observe: unknown kind");
   }

@@ -28,6 +28,7 @@ TTNS_FLAG_AUTOTUNE = 2
 OBS_RDM, OBS_POP, OBS_LOCAL, OBS_NORM, OBS_ENERGY = 0, 1, 2, 3, 4
 OBS_HISTORY, OBS_RECORD_SIZE, OBS_TENSOR, OBS_STATS, OBS_BOND_DIMS = 5, 6, 7, 8, 9
 OBS_STEP_FLOPS = 10
+OBS_ENTROPY = 11
 
 EXPORTED = [
     "ttns_default_opts", "ttns_ohmic_chain", "ttns_workspace_size", "ttns_star_workspace_size",
@@ -317,6 +318,10 @@ class Context:
         """Algorithmic flops of one step of ``tree``: (total, H_eff part)."""
         f = self.ttns_observe(OBS_STEP_FLOPS, tree, n=2)
         return float(f[0]), float(f[1])
+
+    def entropy(self, tree, node):
+        """Entanglement entropy across the bond (node, parent(node))."""
+        return float(self.ttns_observe(OBS_ENTROPY, tree, node, n=1)[0])
 
     def bond_dims(self, tree, n_nodes):
         return self.ttns_observe(OBS_BOND_DIMS, tree, n=n_nodes).astype(int)

@@ -120,6 +120,31 @@ def test_cooperative_executor_equals_wide_at_full_size():
     assert np.abs(hw["energy"] - hc["energy"]).max() <= 1e-12 * max(1.0, np.abs(hw["energy"]).max())
 
 
+@pytest.mark.parametrize("topology", ["star", "er"])
+def test_bond_entropy_matches_oracle(topology):
+    """Entanglement entropy across bonds (root-chain, chain-chain, ER) after
+    a few steps, and zero for the product initial state."""
+    T = _T()
+    m = dict(W.vibronic_small(steps=4), topology=topology)
+    tt, _ = run(m)
+    ctx = T.Context([m], opts=T.default_opts(record_capacity=m["steps"] + 1))
+    n = tt.n
+    nodes = sorted(set([1, 2, 3, n // 2, n - 1]))
+    for v in nodes:
+        assert abs(ctx.entropy(0, v)) < 1e-10
+    ctx.ttns_tdvp_step(m["dt"], m["steps"])
+    for v in nodes:
+        got = ctx.entropy(0, v)
+        ref = tt.bond_entropy(v)
+        assert abs(got - ref) < 1e-8, (v, got, ref)
+    # a later step starts from the root again
+    ctx.ttns_tdvp_step(m["dt"], 1)
+    tt.move_to(0)
+    tt.step(m["dt"])
+    np.testing.assert_allclose(ctx.history()["rdm"][-1], tt.rdm(), atol=1e-10)
+    ctx.close()
+
+
 def test_er_tree_eight_chains_small():
     m = W.vibronic(seed=4, n_chains=8, L=3, d=4, D=6, steps=4, topology="er", er_D=6)
     (hg,), _ = gpu_history([m], m["steps"])

@@ -104,3 +104,42 @@ def test_paper_root_tensor_memory_model():
     D = clamp_bond_dims(parent, phys, [0] + [50] * 14, children)
     root_bytes = phys[0] * np.prod([D[c] for c in children[0]]) * 16
     assert abs(root_bytes / 2 ** 40 - 56.84) < 0.01
+
+
+def _subtree(tree, v):
+    out, stack = [], [v]
+    while stack:
+        u = stack.pop()
+        out.append(u)
+        stack.extend(c for c in range(len(tree.parent)) if tree.parent[c] == u)
+    return sorted(out)
+
+
+@pytest.mark.parametrize("name", list(TREES))
+def test_bond_entropy_matches_full_state_schmidt_values(name):
+    """Entanglement entropy across every bond against the Schmidt
+    decomposition of the full state (subtree legs | the rest); zero for the
+    product initial state."""
+    m = TREES[name]()
+    tree = build_tree(m)
+    t = TTNS(tree)
+    n = len(tree.parent)
+    for v in range(1, n):
+        assert abs(t.bond_entropy(v)) < 1e-12
+    t.move_to(0)
+    for _ in range(3):
+        t.step(m["dt"])
+    psi = t.full_state()
+    dims = [tree.phys[u] for u in range(n)]
+    for v in range(1, n):
+        sub = _subtree(tree, v)
+        assert sub == list(range(v, v + len(sub)))  # pre-order: contiguous legs
+        X = psi.reshape(dims)
+        rest = [u for u in range(n) if u not in sub]
+        M = np.transpose(X, sub + rest).reshape(int(np.prod([dims[u] for u in sub])), -1)
+        s = np.linalg.svd(M, compute_uv=False)
+        p = s ** 2 / np.sum(s ** 2)
+        p = p[p > 1e-300]
+        ref = float(-np.sum(p * np.log(p)))
+        t.move_to(0)
+        assert abs(t.bond_entropy(v) - ref) < 1e-10, (name, v)
