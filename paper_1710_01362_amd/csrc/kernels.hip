@@ -621,9 +621,23 @@ __device__ void body_qr_t(const Op& op, const DevTables& T, Smem& sm, cd* lds) {
       return;
     }
     // u = e_row - Q (Q^H e_row), then a second pass
+    bool nz = false;
     for (int j = threadIdx.x; j < k; j += kBlock) {
       const cd q = Q[(size_t)j * rows + row];
       hb1[j] = make_double2(q.x, -q.y);
+      nz = nz || q.x != 0.0 || q.y != 0.0;
+    }
+    if (!__syncthreads_or(nz)) {
+      // e_row is exactly orthogonal to the span (every coefficient is zero,
+      // as for the unit columns of product-like states): the general path
+      // below would give q_k = e_row and R_kk = <e_row, v> = v[row] exactly
+      for (int r = threadIdx.x; r < rows; r += kBlock) qk[r] = make_double2(r == row ? 1.0 : 0.0, 0.0);
+      if (threadIdx.x == 0) {
+        R[k * cols + k] = v[row];
+        atomicAdd(&tr.stats[0], 1);
+      }
+      __syncthreads();
+      continue;
     }
     for (int r = threadIdx.x; r < rows; r += kBlock) u[r] = make_double2(r == row ? 1.0 : 0.0, 0.0);
     __syncthreads();
