@@ -98,7 +98,8 @@ struct TreeState {
   // H_eff on the matrix cores (empty: the node uses the scalar apply)
   std::vector<std::vector<int>> mode_pre;     // bond-bond pre-stages (ModeDesc ids)
   std::vector<std::vector<int>> mode_groups;  // groups; the first carries the site term
-  std::vector<int> mode_tile;                 // 0 default, 1 small, 2 large tile (autotuner)
+  std::vector<int> mode_tile;                 // 0 default, else the autotuner's tile (op.i1 code:
+                                              // 1 small / 2 large operands, + 4 for 16 columns)
 };
 
 bool in_subtree(const TreeState& t, int node, int v) { return node >= v && node < v + t.sub[v]; }
@@ -242,7 +243,7 @@ struct ttns_ctx {
   // autotuner: the probe build plans every candidate; the final build
   // follows the measured choices
   bool tune_probe = false;
-  std::map<std::string, int> tune_heff;  // node class -> 0 scalar, 1 small tile, 2 large tile
+  std::map<std::string, int> tune_heff;  // node class -> 0 scalar, else the matrix-core tile (op.i1 code)
   std::map<std::string, int> tune_qr;    // QR shape -> 0 one workgroup, k > 0 wide with k workgroups
   std::string tune_report;
 };
@@ -1608,8 +1609,8 @@ int validate_program(ttns_ctx& c, const std::vector<Op>& ops, bool allow_user_xy
         }
         if (m.axis == m.sh.phys_axis || D > mode_max_bond(m.prec) || o.n != m.n_rest ||
             o.axis != dp || o.i0 != m.prec || m.n_e < 1 || m.n_e > kMaxGroup ||
-            o.j != mode_padded(m.prec, D) || o.i1 < 0 || o.i1 > 2 ||
-            (o.i1 == 1 && o.j > mode_small_dp(m.prec)))
+            o.j != mode_padded(m.prec, D) || (o.i1 & ~7) != 0 || (o.i1 & 3) == 3 ||
+            ((o.i1 & 3) == 1 && o.j > mode_small_dp(m.prec)))
           rc.err = "internal: matrix-core group";
         break;
       }
@@ -1911,22 +1912,26 @@ static int autotune(ttns_ctx& c) {
         const ModeDesc& m = c.modes[id];
         small_fits = small_fits && mode_padded(m.prec, m.sh.dims[m.axis]) <= mode_small_dp(m.prec);
       }
-      for (int tile = small_fits ? 1 : 2; tile <= 2; ++tile) {
-        t.mode_tile[v] = tile;
-        ops.clear();
-        b.mode_apply(v, vj, t.dev.W);
-        lz(1);
-        if ((rc = time_ops(c, ops, kReps, ms))) return rc;
-        snprintf(line, sizeof line, ", matrix cores %s tile %.4f ms", tile == 1 ? "small" : "large", ms);
-        l += line;
-        if (ms < best) {
-          best = ms;
-          choice = tile;
+      auto tile_name = [](int tl) {
+        return std::string((tl & 3) == 1 ? "small" : "large") + ((tl & 4) ? " tile x16" : " tile x64");
+      };
+      for (int tile = small_fits ? 1 : 2; tile <= 2; ++tile)
+        for (int narrow = 0; narrow <= 4; narrow += 4) {
+          t.mode_tile[v] = tile | narrow;
+          ops.clear();
+          b.mode_apply(v, vj, t.dev.W);
+          lz(1);
+          if ((rc = time_ops(c, ops, kReps, ms))) return rc;
+          snprintf(line, sizeof line, ", matrix cores %s %.4f ms", tile_name(tile | narrow).c_str(), ms);
+          l += line;
+          if (ms < best) {
+            best = ms;
+            choice = tile | narrow;
+          }
         }
-      }
       t.mode_tile[v] = 0;
       c.tune_heff[key] = choice;
-      rep += l + " -> " + (choice == 0 ? "scalar" : choice == 1 ? "small tile" : "large tile") + "\n";
+      rep += l + " -> " + (choice == 0 ? std::string("scalar") : tile_name(choice)) + "\n";
     }
   }
   // tall QR shapes of the step programs

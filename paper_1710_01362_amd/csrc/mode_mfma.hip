@@ -5,12 +5,12 @@
 //   y[s] (+)= sum_e E_e x_axis Z_{e,s},   Z_{e,s} = sum_o coef_e g_e(s,o) src[s + o],
 // with g_e(s,o) = op_e[s][s + o] (the identity when the term has no local
 // operator).  Workgroup (blockIdx.y = output physical index s, blockIdx.x =
-// tile of kModeNT "rest" columns, i.e. all indices other than the bond axis
-// and the physical leg).  For every term e the workgroup stages the real form
+// tile of 64 or 16 "rest" columns, i.e. all indices other than the bond
+// axis and the physical leg).  For every term e the workgroup stages the real form
 //   A_e = [[Re E_e, -Im E_e], [Im E_e, Re E_e]]   (2D x 2D, zero-padded to DP)
-// and B_e = [Re Z_{e,s}; Im Z_{e,s}] (2D x kModeNT) in LDS and accumulates
-// Y += A_e B_e on 16x16 MFMA tiles: wavefront w owns output columns
-// 16w..16w+15 and every row block.  A_e does not depend on s and B_e needs
+// and B_e = [Re Z_{e,s}; Im Z_{e,s}] (2D x columns) in LDS and accumulates
+// Y += A_e B_e on 16x16 MFMA tiles (which wavefront owns which output
+// tiles depends on the column tile, see k_mode).  A_e does not depend on s and B_e needs
 // only the band of g_e, so every global load is a plain independent load of
 // an environment matrix or a source slice, issued in batches.
 // Operand layouts (all precisions): lane l supplies A[l % 16][k-group l / 16]
@@ -38,6 +38,8 @@ typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 
 int mode_max_bond(int prec) { return prec == TTNS_FP64 ? 48 : 64; }
 int mode_small_dp(int prec) { return prec == TTNS_FP64 ? 48 : 64; }
+// 16-column tiles when 64-column ones would give fewer workgroups than CUs
+bool mode_default_narrow(int n_rest, int d) { return (long)((n_rest + 63) / 64) * d < 256; }
 int mode_padded(int prec, int D) {
   const int pad = prec == TTNS_BF16X3 ? 32 : 16;
   return (2 * D + pad - 1) / pad * pad;
@@ -45,7 +47,6 @@ int mode_padded(int prec, int D) {
 
 namespace {
 
-constexpr int NT = kModeNT;  // columns per workgroup (4 wavefronts x 16)
 
 __device__ __forceinline__ unsigned short bf16_bits(float x) {
   // round to nearest even
@@ -98,32 +99,36 @@ __device__ __forceinline__ void put(typename Prec<PREC>::T* p0, typename Prec<PR
   }
 }
 
-template <int PREC, int DPMAX>
+template <int PREC, int DPMAX, int TN>
 struct ModeSmem {
   using T = typename Prec<PREC>::T;
   static constexpr bool kSplit = PREC == TTNS_BF16X3;
   static constexpr int LDA = DPMAX + (kSplit ? 8 : 1);  // row stride of A and column stride of B
   static constexpr int PLANES = kSplit ? 2 : 1;
   static constexpr size_t kA = (size_t)PLANES * DPMAX * LDA * sizeof(T);
-  static constexpr size_t kB = (size_t)PLANES * NT * LDA * sizeof(T);
-  static constexpr size_t kY = (size_t)DPMAX * NT * sizeof(double);
+  static constexpr size_t kB = (size_t)PLANES * TN * LDA * sizeof(T);
+  static constexpr size_t kY = (size_t)DPMAX * TN * sizeof(double);
   static constexpr size_t kBytes = (kA + kB > kY ? kA + kB : kY);
 };
 
-template <int PREC, int DPMAX>
+// TN: rest columns per workgroup.  TN = 64: wavefront w owns columns
+// 16w..16w+15 and every row block; TN = 16: all wavefronts share the 16
+// columns and wavefront w owns row blocks w, w+4, ... (four times more
+// workgroups for nodes with few rest columns).
+template <int PREC, int DPMAX, int TN>
 __global__ __launch_bounds__(kBlock) void k_mode(Op op, DevTables Tb) {
   using P = Prec<PREC>;
-  using S = ModeSmem<PREC, DPMAX>;
+  using S = ModeSmem<PREC, DPMAX, TN>;
   using T = typename P::T;
   constexpr bool kSplit = S::kSplit;
   constexpr int LDA = S::LDA;
   // A planes, then B planes; the epilogue reuses the space for Y (doubles)
   __shared__ __align__(16) unsigned char smem[S::kBytes];
-  __shared__ int roff[NT];
+  __shared__ int roff[TN];
   T* A0 = reinterpret_cast<T*>(smem);
   T* A1 = A0 + DPMAX * LDA;
   T* B0 = reinterpret_cast<T*>(smem + S::kA);
-  T* B1 = B0 + NT * LDA;
+  T* B1 = B0 + TN * LDA;
 
   const ModeDesc& m = Tb.modes[op.desc];
   const Shape& sh = m.sh;
@@ -133,20 +138,20 @@ __global__ __launch_bounds__(kBlock) void k_mode(Op op, DevTables Tb) {
   const int D2 = 2 * D;
   const int DP = (D2 + P::KPAD - 1) / P::KPAD * P::KPAD;
   const int s = blockIdx.y;
-  const int r0 = blockIdx.x * NT;
-  const int ncol = min(NT, m.n_rest - r0);
+  const int r0 = blockIdx.x * TN;
+  const int ncol = min(TN, m.n_rest - r0);
   const cd* src = op.p0 ? op.p0 : m.src;
   cd* y = op.p1 ? op.p1 : m.y;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const bool bfast = sa == 1;  // bond index fastest in memory
 
-  for (int c = t; c < NT; c += kBlock) roff[c] = c < ncol ? rest_offset(sh, ax, r0 + c) : 0;
+  for (int c = t; c < TN; c += kBlock) roff[c] = c < ncol ? rest_offset(sh, ax, r0 + c) : 0;
   // zero padding: A rows and columns >= 2D, B rows >= 2D (never rewritten)
   for (int i = t; i < DP * DP; i += kBlock) {
     const int row = i / DP, col = i % DP;
     if (row >= D2 || col >= D2) put<PREC>(A0, A1, row * LDA + col, 0.0);
   }
-  for (int i = t; i < NT * (DP - D2); i += kBlock) {
+  for (int i = t; i < TN * (DP - D2); i += kBlock) {
     const int c = i / (DP - D2), k = D2 + i % (DP - D2);
     put<PREC>(B0, B1, c * LDA + k, 0.0);
   }
@@ -156,9 +161,9 @@ __global__ __launch_bounds__(kBlock) void k_mode(Op op, DevTables Tb) {
 #pragma unroll
   for (int i = 0; i < DPMAX / 16; ++i) acc[i] = Acc{0, 0, 0, 0};
 
-  constexpr int kU = (DPMAX / 2) * NT / kBlock;  // B elements (complex) per thread, D <= DPMAX / 2
+  constexpr int kU = ((DPMAX / 2) * TN + kBlock - 1) / kBlock;  // B elements (complex) per thread, D <= DPMAX / 2
   constexpr int kUA = (DPMAX / 2) * (DPMAX / 2) / kBlock + 1;
-  const int nz = D * NT;  // complex B elements
+  const int nz = D * TN;  // complex B elements
   for (int e = 0; e < m.n_e; ++e) {
     const cd* op_e = m.op[e];
     const double coef = m.coef[e];
@@ -211,8 +216,8 @@ __global__ __launch_bounds__(kBlock) void k_mode(Op op, DevTables Tb) {
             b = i % D;
             c = i / D;
           } else {
-            c = i % NT;
-            b = i / NT;
+            c = i % TN;
+            b = i / TN;
           }
           v[u] = (i < nz && c < ncol) ? base[b * sa + roff[c]] : cz();
         }
@@ -228,8 +233,8 @@ __global__ __launch_bounds__(kBlock) void k_mode(Op op, DevTables Tb) {
             b = i % D;
             c = i / D;
           } else {
-            c = i % NT;
-            b = i / NT;
+            c = i % TN;
+            b = i / TN;
           }
           put<PREC>(B0, B1, c * LDA + b, z[u].x);
           put<PREC>(B0, B1, c * LDA + D + b, z[u].y);
@@ -237,7 +242,7 @@ __global__ __launch_bounds__(kBlock) void k_mode(Op op, DevTables Tb) {
       }
     }
     __syncthreads();
-    const int col = w * 16 + (lane & 15);
+    const int col = (TN == 64 ? w * 16 : 0) + (lane & 15);
     const int kq = lane >> 4;
     for (int kk = 0; kk < DP; kk += P::KS) {
       if constexpr (kSplit) {
@@ -250,6 +255,7 @@ __global__ __launch_bounds__(kBlock) void k_mode(Op op, DevTables Tb) {
 #pragma unroll
         for (int bi = 0; bi < DPMAX / 16; ++bi) {
           if (bi * 16 >= DP) break;
+          if (TN == 16 && (bi & 3) != w) continue;
           const int row = bi * 16 + (lane & 15);
           bf8v ah, al;
           for (int q = 0; q < 8; ++q) {
@@ -265,6 +271,7 @@ __global__ __launch_bounds__(kBlock) void k_mode(Op op, DevTables Tb) {
 #pragma unroll
         for (int bi = 0; bi < DPMAX / 16; ++bi) {
           if (bi * 16 >= DP) break;
+          if (TN == 16 && (bi & 3) != w) continue;
           const T av = A0[(bi * 16 + (lane & 15)) * LDA + kk + kq];
           if constexpr (PREC == TTNS_FP64)
             acc[bi] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[bi], 0, 0, 0);
@@ -279,25 +286,26 @@ __global__ __launch_bounds__(kBlock) void k_mode(Op op, DevTables Tb) {
   // pair real and imaginary rows
   double* Ys = reinterpret_cast<double*>(smem);
   {
-    const int col = w * 16 + (lane & 15);
+    const int col = (TN == 64 ? w * 16 : 0) + (lane & 15);
 #pragma unroll
     for (int bi = 0; bi < DPMAX / 16; ++bi) {
       if (bi * 16 >= DP) break;
+      if (TN == 16 && (bi & 3) != w) continue;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         // accumulator layout: FP64 16x16x4 holds row 4q + lane/16, the FP32
         // accumulating forms hold row 4 (lane/16) + q (column lane % 16)
         const int row = PREC == TTNS_FP64 ? 4 * q + (lane >> 4) : 4 * (lane >> 4) + q;
-        Ys[(bi * 16 + row) * NT + col] = (double)acc[bi][q];
+        Ys[(bi * 16 + row) * TN + col] = (double)acc[bi][q];
       }
     }
   }
   __syncthreads();
-  for (int i = t; i < D * NT; i += kBlock) {
-    const int a = i / NT, c = i % NT;
+  for (int i = t; i < D * TN; i += kBlock) {
+    const int a = i / TN, c = i % TN;
     if (c >= ncol) continue;
     const int off = s * sp + a * sa + roff[c];
-    cd v = make_double2(Ys[a * NT + c], Ys[(D + a) * NT + c]);
+    cd v = make_double2(Ys[a * TN + c], Ys[(D + a) * TN + c]);
     if (m.accumulate) {
       v = cadd(v, y[off]);
     } else if (m.site) {
@@ -311,29 +319,38 @@ __global__ __launch_bounds__(kBlock) void k_mode(Op op, DevTables Tb) {
   }
 }
 
-template <int PREC>
-hipError_t launch_prec(const Op& op, const DevTables& t, hipStream_t s, dim3 grid) {
-  // op.j: padded real operand size DP of this group; op.i1: tile chosen by
-  // the autotuner (1 small, 2 large) or 0 (the small tile when it fits)
-  const bool small = op.i1 == 1 || (op.i1 == 0 && op.j <= Prec<PREC>::SMALL);
+template <int PREC, int TN>
+hipError_t launch_tn(const Op& op, const DevTables& t, hipStream_t s, int n_rest, int d, bool small) {
+  const dim3 grid((n_rest + TN - 1) / TN, d);
   if (small)
-    hipLaunchKernelGGL((k_mode<PREC, Prec<PREC>::SMALL>), grid, dim3(kBlock), 0, s, op, t);
+    hipLaunchKernelGGL((k_mode<PREC, Prec<PREC>::SMALL, TN>), grid, dim3(kBlock), 0, s, op, t);
   else
-    hipLaunchKernelGGL((k_mode<PREC, Prec<PREC>::BIG>), grid, dim3(kBlock), 0, s, op, t);
+    hipLaunchKernelGGL((k_mode<PREC, Prec<PREC>::BIG, TN>), grid, dim3(kBlock), 0, s, op, t);
   return hipGetLastError();
+}
+
+// op.j: padded real operand size DP of this group; op.i1: the tile chosen by
+// the autotuner (bit 0: small operand tile, bit 1: large, bit 2: 16 columns
+// per workgroup instead of 64) or 0 (default: the small tile when it fits,
+// 16 columns when 64-column tiles would leave the GPU under-filled)
+template <int PREC>
+hipError_t launch_prec(const Op& op, const DevTables& t, hipStream_t s, int n_rest, int d) {
+  const int tile = op.i1 & 3;
+  const bool small = tile == 1 || (tile == 0 && op.j <= Prec<PREC>::SMALL);
+  const bool narrow = op.i1 ? (op.i1 & 4) != 0 : mode_default_narrow(n_rest, d);
+  return narrow ? launch_tn<PREC, 16>(op, t, s, n_rest, d, small) : launch_tn<PREC, 64>(op, t, s, n_rest, d, small);
 }
 
 }  // namespace
 
 hipError_t launch_mode(const Op& op, const DevTables& t, hipStream_t s, int prec, int n_rest, int d) {
-  const dim3 grid((n_rest + NT - 1) / NT, d);
   switch (prec) {
     case TTNS_FP64:
-      return launch_prec<TTNS_FP64>(op, t, s, grid);
+      return launch_prec<TTNS_FP64>(op, t, s, n_rest, d);
     case TTNS_FP32:
-      return launch_prec<TTNS_FP32>(op, t, s, grid);
+      return launch_prec<TTNS_FP32>(op, t, s, n_rest, d);
     case TTNS_BF16X3:
-      return launch_prec<TTNS_BF16X3>(op, t, s, grid);
+      return launch_prec<TTNS_BF16X3>(op, t, s, n_rest, d);
     default:
       return hipErrorInvalidValue;
   }

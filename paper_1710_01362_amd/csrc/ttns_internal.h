@@ -236,12 +236,13 @@ struct GridBar {
 int coop_max_blocks();
 hipError_t launch_coop(const Op* dev_ops, int begin, int end, const DevTables& t, GridBar* bar, int blocks,
                        hipStream_t s);
-// MFMA limits: bond dimension per precision, columns per workgroup tile
-constexpr int kModeNT = 64;
+// MFMA limits: largest bond dimension per precision
 int mode_max_bond(int prec);
 // padded real operand size (2D rounded up to the MFMA K granule) of a group
 int mode_padded(int prec, int D);
 // largest padded size the small matrix-core tile takes
 int mode_small_dp(int prec);
+// default column tile: 16 columns when 64-column tiles give too few workgroups
+bool mode_default_narrow(int n_rest, int d);
 
 }  // namespace ttns

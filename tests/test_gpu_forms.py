@@ -60,6 +60,13 @@ def test_fp64_matrix_cores_root_of_reference_tree():
 
 
 @pytest.mark.parametrize("precision", [1, 2], ids=["fp32", "bf16x3"])
+def test_reduced_precision_root_of_reference_tree(precision):
+    """The 5 x 20^4 root on 64-column tiles (small trees use 16-column ones)."""
+    m = W.vibronic_reference()
+    _apply_vs_oracle(m, precision, [0], 2e-5)
+
+
+@pytest.mark.parametrize("precision", [1, 2], ids=["fp32", "bf16x3"])
 @pytest.mark.parametrize("topology", ["star", "er"])
 def test_reduced_precision_apply(precision, topology):
     m = dict(W.vibronic(seed=5, n_chains=4, L=5, d=6, D=6, steps=2), topology=topology)
