@@ -489,6 +489,8 @@ __device__ double qr_subtract(const cd* Q, cd* v, int rows, int k, const cd* h) 
   return n2;
 }
 
+constexpr int kQrWRows = 768;  // rows whose span weights the QR keeps in LDS (what the LDS budget leaves)
+
 // LDS budget of the QR (complex entries): Q columns plus two row vectors.
 constexpr int kQrLds = kQrLdsEntries;  // 137.5 KiB: a 400 x 20 matrix plus two vectors
 
@@ -500,7 +502,7 @@ constexpr int kQrLds = kQrLdsEntries;  // 137.5 KiB: a 400 x 20 matrix plus two 
 // orthogonalised twice.  Q and the work vectors live in LDS (`lds`, kQrLds
 // entries) when they fit, else in the tree's global scratch.
 template <bool kLds>
-__device__ void body_qr_t(const Op& op, const DevTables& T, Smem& sm, cd* lds) {
+__device__ void body_qr_t(const Op& op, const DevTables& T, Smem& sm, cd* lds, double* wrow) {
   const TreeDev& tr = T.trees[op.tree];
   const Shape& sh = T.descs[op.desc].sh;
   const int ax = op.axis;
@@ -518,6 +520,10 @@ __device__ void body_qr_t(const Op& op, const DevTables& T, Smem& sm, cd* lds) {
   __shared__ cd hb1[64], hb2[64];
   // gather A (column-major), |A|_F^2 and the squared norm of every column
   __shared__ double colnrm[64];
+  // wrow[r] = sum_{j<k} |Q_j[r]|^2, kept up to date as columns are finished
+  // (when rows <= kQrWRows), so the completion search reads one number per
+  // candidate instead of k
+  const bool track = wrow != nullptr && rows <= kQrWRows;
   for (int c = threadIdx.x; c < cols; c += kBlock) colnrm[c] = 0.0;
   __syncthreads();
   for (int r = threadIdx.x; r < rows; r += kBlock) {
@@ -539,6 +545,8 @@ __device__ void body_qr_t(const Op& op, const DevTables& T, Smem& sm, cd* lds) {
     }
   }
   for (int i = threadIdx.x; i < cols * cols; i += kBlock) R[i] = cz();
+  if (track)
+    for (int r = threadIdx.x; r < rows; r += kBlock) wrow[r] = 0.0;
   __syncthreads();
   double nrm = 0.0;
   for (int c = 0; c < cols; ++c) nrm += colnrm[c];
@@ -570,13 +578,20 @@ __device__ void body_qr_t(const Op& op, const DevTables& T, Smem& sm, cd* lds) {
     // a column no longer than tol is deficient whatever its projections:
     // one pass gives its R entries and residual; otherwise two passes
     const bool tiny = sqrt(colnrm[k]) <= tol;
-    qr_project(Q, v, rows, k, hb1);
     double rn;
-    if (tiny) {
+    if (colnrm[k] == 0.0) {
+      // an exactly zero column: every projection and the residual are
+      // exactly zero, as the passes below would compute them
+      for (int j = threadIdx.x; j < k; j += kBlock) hb1[j] = hb2[j] = cz();
+      rn = 0.0;
+      __syncthreads();
+    } else if (tiny) {
+      qr_project(Q, v, rows, k, hb1);
       rn = sqrt(block_sum(make_double2(qr_subtract(Q, v, rows, k, hb1), 0.0), sm).x);
       for (int j = threadIdx.x; j < k; j += kBlock) hb2[j] = cz();
       __syncthreads();
     } else {
+      qr_project(Q, v, rows, k, hb1);
       qr_subtract(Q, v, rows, k, hb1);
       qr_project(Q, v, rows, k, hb2);
       rn = sqrt(block_sum(make_double2(qr_subtract(Q, v, rows, k, hb2), 0.0), sm).x);
@@ -585,7 +600,11 @@ __device__ void body_qr_t(const Op& op, const DevTables& T, Smem& sm, cd* lds) {
     cd* qk = Q + (size_t)k * rows;
     if (rn > tol) {
       const double ir = 1.0 / rn;
-      for (int r = threadIdx.x; r < rows; r += kBlock) qk[r] = cscale(v[r], ir);
+      for (int r = threadIdx.x; r < rows; r += kBlock) {
+        const cd q = cscale(v[r], ir);
+        qk[r] = q;
+        if (track) wrow[r] += cabs2(q);
+      }
       if (threadIdx.x == 0) R[k * cols + k] = make_double2(rn, 0.0);
       __syncthreads();
       continue;
@@ -599,15 +618,21 @@ __device__ void body_qr_t(const Op& op, const DevTables& T, Smem& sm, cd* lds) {
         bool ok = false;
         if (n < rows) {
           const int row = qr_candidate_row(sh, ax, n);
-          double s = 0.0, s1 = 0.0;
-          int j = 0;
+          double w;
+          if (track) {
+            w = wrow[row];
+          } else {
+            double s = 0.0, s1 = 0.0;
+            int j = 0;
 #pragma unroll 2
-          for (; j + 1 < k; j += 2) {
-            s += cabs2(Q[(size_t)j * rows + row]);
-            s1 += cabs2(Q[(size_t)(j + 1) * rows + row]);
+            for (; j + 1 < k; j += 2) {
+              s += cabs2(Q[(size_t)j * rows + row]);
+              s1 += cabs2(Q[(size_t)(j + 1) * rows + row]);
+            }
+            if (j < k) s += cabs2(Q[(size_t)j * rows + row]);
+            w = s + s1;
           }
-          if (j < k) s += cabs2(Q[(size_t)j * rows + row]);
-          ok = (1.0 - (s + s1)) > thr;
+          ok = (1.0 - w) > thr;
         }
         const unsigned long long m = __ballot(ok);
         if (m) chosen = base + __ffsll((long long)m) - 1;
@@ -631,7 +656,10 @@ __device__ void body_qr_t(const Op& op, const DevTables& T, Smem& sm, cd* lds) {
       // e_row is exactly orthogonal to the span (every coefficient is zero,
       // as for the unit columns of product-like states): the general path
       // below would give q_k = e_row and R_kk = <e_row, v> = v[row] exactly
-      for (int r = threadIdx.x; r < rows; r += kBlock) qk[r] = make_double2(r == row ? 1.0 : 0.0, 0.0);
+      for (int r = threadIdx.x; r < rows; r += kBlock) {
+        qk[r] = make_double2(r == row ? 1.0 : 0.0, 0.0);
+        if (track && r == row) wrow[r] += 1.0;
+      }
       if (threadIdx.x == 0) {
         R[k * cols + k] = v[row];
         atomicAdd(&tr.stats[0], 1);
@@ -648,6 +676,7 @@ __device__ void body_qr_t(const Op& op, const DevTables& T, Smem& sm, cd* lds) {
     for (int r = threadIdx.x; r < rows; r += kBlock) {
       const cd q = cscale(u[r], iu);
       qk[r] = q;
+      if (track) wrow[r] += cabs2(q);
       rkk = cjfma(q, v[r], rkk);
     }
     rkk = block_sum(rkk, sm);
@@ -664,12 +693,20 @@ __device__ void body_qr_t(const Op& op, const DevTables& T, Smem& sm, cd* lds) {
   }
 }
 
+// kTrack: keep the span weights in LDS (the wide executor's QR kernel); the
+// one-workgroup executors' kernels hold other LDS buffers and do without.
+template <bool kTrack>
 __device__ void body_qr(const Op& op, const DevTables& T, Smem& sm, cd* lds) {
   const Shape& sh = T.descs[op.desc].sh;
   const int cols = sh.dims[op.axis];
   const int rows = sh.size / cols;
-  if ((size_t)rows * (cols + 2) <= (size_t)kQrLds) body_qr_t<true>(op, T, sm, lds);
-  else body_qr_t<false>(op, T, sm, nullptr);
+  double* wrow = nullptr;
+  if constexpr (kTrack) {
+    __shared__ double w[kQrWRows];
+    wrow = w;
+  }
+  if ((size_t)rows * (cols + 2) <= (size_t)kQrLds) body_qr_t<true>(op, T, sm, lds, wrow);
+  else body_qr_t<false>(op, T, sm, nullptr, wrow);
 }
 
 // ------------------------------------------------------------ wide QR
@@ -1186,12 +1223,15 @@ __global__ __launch_bounds__(kBlock) void k_op(Op op, DevTables T) {
   } else if constexpr (TY == OP_ORTH1) {
     if (body_orth1(op, T, vb, sm) && last_block(tr.counter, op.nvb, sm)) fin_orth1(op, T, op.nvb, sm);
   } else if constexpr (TY == OP_ORTH2) {
-    if (body_orth2(op, T, vb) && last_block(tr.counter, op.nvb, sm)) fin_orth2(op, T);
+    // fin_orth2 reads only scalars fixed before this launch (beta comes from
+    // the norm identity of the first pass), so workgroup 0 can run it
+    // without waiting for the others: no ticket
+    if (body_orth2(op, T, vb) && vb == 0) fin_orth2(op, T);
   } else if constexpr (TY == OP_COMBINE) {
     body_combine(op, T, vb, sm);
   } else if constexpr (TY == OP_QR) {
     __shared__ cd qr_lds[kQrLds];
-    body_qr(op, T, sm, qr_lds);
+    body_qr<true>(op, T, sm, qr_lds);
   } else if constexpr (TY == OP_QRW) {
     if (body_qrw(op, T, vb, sm) && last_block(tr.counter, op.nvb, sm)) fin_qrw(op, T, op.nvb, sm);
   } else if constexpr (TY == OP_CONTRACT) {
@@ -1258,7 +1298,7 @@ __global__ __launch_bounds__(kBlock) void k_persistent(const Op* __restrict__ op
         for (int vb = 0; vb < nvb; ++vb) body_combine(op, T, vb, sm);
         break;
       case OP_QR:
-        body_qr(op, T, sm, qr_lds);
+        body_qr<false>(op, T, sm, qr_lds);
         break;
       case OP_CONTRACT:
         for (int vb = 0; vb < nvb; ++vb) body_contract(op, T, vb, sm, qr_lds);
@@ -1419,7 +1459,7 @@ __global__ __launch_bounds__(kBlock) void k_coop(const Op* __restrict__ ops, int
         for (int vb = b; vb < nvb; vb += G) body_combine(op, T, vb, sm);
         break;
       case OP_QR:
-        if (b == 0) body_qr(op, T, sm, qr_lds);
+        if (b == 0) body_qr<false>(op, T, sm, qr_lds);
         break;
       case OP_CONTRACT:
         for (int vb = b; vb < nvb; vb += G) body_contract(op, T, vb, sm, qr_lds);
