@@ -104,6 +104,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--executor", default="auto", choices=["auto", "wide", "persistent", "cooperative"])
+    ap.add_argument("--coop-workgroups", type=int, default=0,
+                    help="workgroups of the cooperative executor (0: library default)")
     ap.add_argument("--autotune", action="store_true",
                     help="time the H_eff and QR variants at build and plan the fastest")
     args = ap.parse_args()
@@ -124,7 +126,8 @@ def main():
     ex = {"auto": T.TTNS_EXEC_AUTO, "wide": T.TTNS_EXEC_WIDE, "persistent": T.TTNS_EXEC_PERSISTENT,
           "cooperative": T.TTNS_EXEC_COOPERATIVE}[args.executor]
     ctx = T.Context(models, opts=T.default_opts(record_capacity=total + 1, executor=ex,
-                                                precision=PREC[args.precision], flags=flags))
+                                                precision=PREC[args.precision], flags=flags,
+                                                coop_workgroups=args.coop_workgroups))
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t_build
     dt = models[0]["dt"]
@@ -155,7 +158,8 @@ def main():
         "config": {"workload": desc, "trees": len(models), "site_updates_per_step": upd_per_step,
                    "krylov": models[0]["krylov"],
                    "executor": "one persistent workgroup per tree" if persistent
-                   else ("all workgroups per operation, grid barriers, one cooperative launch per stretch"
+                   else ("the workgroups of one XCD per operation, barriers in its L2, one cooperative "
+                         "launch per stretch"
                          if args.executor == "cooperative"
                          else "one kernel per operation, replayed as a HIP graph"),
                    "autotuned": bool(args.autotune), "build_s": round(t_build, 2)},

@@ -56,13 +56,16 @@ extern "C" {
 #define TTNS_EXEC_AUTO 0
 #define TTNS_EXEC_WIDE 1       /* each operation spread over many workgroups */
 #define TTNS_EXEC_PERSISTENT 2 /* one workgroup runs a whole tree's step     */
-#define TTNS_EXEC_COOPERATIVE 3 /* 32 co-resident workgroups run the step
-                                   program together, a grid barrier between
-                                   operations, one cooperative launch per
-                                   stretch between matrix-core launches
-                                   (slower than TTNS_EXEC_WIDE on MI355X:
-                                   a grid barrier costs more than a kernel
-                                   boundary in a replayed graph)           */
+#define TTNS_EXEC_COOPERATIVE 3 /* the workgroups of ONE XCD run stretches of
+                                   the step program together, a barrier
+                                   between operations (no L2 write-back:
+                                   the members share that XCD's L2); ops
+                                   too wide for one XCD and the matrix-core
+                                   groups are launched on their own, one
+                                   cooperative launch per stretch between
+                                   them.  Refused (TTNS_EDEVICE) where the
+                                   dispatcher does not deal workgroups
+                                   round-robin over the XCDs.            */
 
 /* option flags */
 #define TTNS_FLAG_MFMA_ALL 1u  /* matrix-core H_eff for every node whose bonds
@@ -165,6 +168,8 @@ typedef struct {
   int32_t record_capacity;   /* records kept on the device (>= 1)            */
   int32_t executor;          /* TTNS_EXEC_*                                  */
   uint32_t flags;            /* TTNS_FLAG_* (0 by default)                   */
+  int32_t coop_workgroups;   /* TTNS_EXEC_COOPERATIVE: workgroups on the one
+                                XCD (0: 32; capped at what fits on an XCD) */
 } ttns_opts;
 
 typedef struct ttns_ctx ttns_ctx;

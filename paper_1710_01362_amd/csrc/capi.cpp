@@ -40,7 +40,8 @@ constexpr int kMaxContractVb = 64;
 constexpr int kMfmaMinSize = 16384;  // nodes this large use the matrix cores
 constexpr size_t kGraphSegment = 8192;  // launches per captured graph
 constexpr int kQrOneGroupRows = 4096;   // tallest QR left to one workgroup
-constexpr int kCoopBlocks = 32;         // grid of the cooperative executor
+constexpr int kCoopMembers = 32;        // default workgroups of the cooperative executor
+constexpr int kCoopWideVbs = 8;         // ops over more than this many vbs per member run wide
 
 // Channel of an environment: the block Hamiltonian (kind 0), one end of a
 // two-node term (kind 1: term k, end 0 = node_a / 1 = node_b) or a recorded
@@ -218,12 +219,14 @@ struct ttns_ctx {
   std::vector<hipGraphExec_t> gexecs;
   bool persistent = false;
   bool coop = false;               // cooperative executor
-  int coop_blocks = 0;             // its grid size
+  int coop_members = 0;            // its workgroups (all on one XCD)
+  int coop_stride = 1;             // XCDs the dispatcher deals workgroups over
+  unsigned coop_xcc = 0;           // XCC id of workgroup 0
   size_t o_bar = 0;                // its GridBar
   GridBar* d_bar = nullptr;
   struct Launch {
     int begin, end;  // a cooperative stretch of the step program, or
-    int single;      // >= 0: one op launched on its own (matrix-core groups)
+    int single;      // >= 0: one op launched on its own (matrix-core groups, wide ops)
   };
   std::vector<Launch> coop_plan;
   bool profile = false;
@@ -1322,6 +1325,8 @@ int prepare(ttns_ctx& c, std::vector<TreeState>&& trees, const ttns_opts* opts, 
   if (o.precision < TTNS_FP64 || o.precision > TTNS_BF16X3) return fail(TTNS_EINVAL, "bad precision");
   if (o.executor < TTNS_EXEC_AUTO || o.executor > TTNS_EXEC_COOPERATIVE) return fail(TTNS_EINVAL, "bad executor");
   if (o.flags & ~(TTNS_FLAG_MFMA_ALL | TTNS_FLAG_AUTOTUNE)) return fail(TTNS_EINVAL, "unknown option flags");
+  if (o.coop_workgroups < 0 || o.coop_workgroups > kXccProbe)
+    return fail(TTNS_EINVAL, "coop_workgroups must be in [0, 1024]");
   c.opts = o;
   c.trees = std::move(trees);
   c.coop = o.executor == TTNS_EXEC_COOPERATIVE;
@@ -1487,22 +1492,45 @@ int prepare(ttns_ctx& c, std::vector<TreeState>&& trees, const ttns_opts* opts, 
   if (c.persistent || c.coop)
     if ((rc = upload(c, c.o_prog, persistent_prog.data(), persistent_prog.size() * sizeof(Op)))) return rc;
   if (c.coop) {
-    // stretches between matrix-core launches
+    // how the dispatcher deals the workgroups of a cooperative launch over
+    // the XCDs: workgroup b to XCD (b mod stride) is what the members' L2
+    // sharing relies on; any other dealing refuses the executor
+    const int maxb = coop_max_blocks();
+    const int pb = std::min(maxb, kXccProbe);
+    if (pb < 1) return fail(TTNS_EDEVICE, "cooperative launch not available on this device");
+    HIPCHK(probe_xcc_map(c.d_bar, pb, c.stream));
+    std::vector<unsigned> ids(pb);
+    HIPCHK(hipMemcpyAsync(ids.data(), c.d_bar->xcc, pb * sizeof(unsigned), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    int stride = pb;
+    for (int b = 1; b < pb; ++b)
+      if (ids[b] == ids[0]) {
+        stride = b;
+        break;
+      }
+    bool dealt = true;
+    for (int b = 0; b < pb; ++b) dealt = dealt && ids[b] == ids[b % stride];
+    for (int x = 0; x < stride; ++x)
+      for (int y = x + 1; y < stride; ++y) dealt = dealt && ids[x] != ids[y];
+    if (!dealt) return fail(TTNS_EDEVICE, "cooperative executor: workgroups are not dealt round-robin over the XCDs");
+    c.coop_stride = stride;
+    c.coop_xcc = ids[0];
+    const int want = c.opts.coop_workgroups > 0 ? c.opts.coop_workgroups : kCoopMembers;
+    c.coop_members = std::max(1, std::min(want, maxb / stride));
+    // stretches between the ops launched on their own: matrix-core groups
+    // and ops too wide for one XCD
     c.coop_plan.clear();
     int start = 0;
+    const int wide_vbs = kCoopWideVbs * c.coop_members;
     for (int i = 0; i <= (int)persistent_prog.size(); ++i) {
-      const bool single = i < (int)persistent_prog.size() && persistent_prog[i].type == OP_MODE;
+      const bool single = i < (int)persistent_prog.size() &&
+                          (persistent_prog[i].type == OP_MODE || persistent_prog[i].nvb > wide_vbs);
       if (i == (int)persistent_prog.size() || single) {
         if (i > start) c.coop_plan.push_back({start, i, -1});
         if (single) c.coop_plan.push_back({0, 0, i});
         start = i + 1;
       }
     }
-    // 32 workgroups measured best on the five-level tree (8: 814 ms/step,
-    // 32: 437, 96: 500, all resident: 746): the barrier's cost grows with
-    // the number of arriving workgroups faster than the ops shrink
-    c.coop_blocks = std::min(coop_max_blocks(), kCoopBlocks);
-    if (c.coop_blocks < 1) return fail(TTNS_EDEVICE, "cooperative launch not available on this device");
   }
   if ((rc = upload(c, c.o_begin, c.tree_begin.data(), c.tree_begin.size() * sizeof(int)))) return rc;
   if ((rc = upload(c, c.o_end, c.tree_end.data(), c.tree_end.size() * sizeof(int)))) return rc;
@@ -1807,6 +1835,7 @@ void ttns_default_opts(ttns_opts* o) {
   o->record_capacity = 1;
   o->executor = TTNS_EXEC_AUTO;
   o->flags = 0;
+  o->coop_workgroups = 0;
 }
 
 const char* ttns_last_error(void) { return g_err.c_str(); }
@@ -2081,7 +2110,9 @@ int ttns_tdvp_step(ttns_ctx* c, double dt, int32_t n_steps) {
     for (int s = 0; s < n_steps; ++s)
       for (const auto& L : c->coop_plan) {
         if (L.single >= 0) HIPCHK(launch_op(c->step_ops[L.single], c->tables, c->stream));
-        else HIPCHK(launch_coop(c->d_ops, L.begin, L.end, c->tables, c->d_bar, c->coop_blocks, c->stream));
+        else
+          HIPCHK(launch_coop(c->d_ops, L.begin, L.end, c->tables, c->d_bar, c->coop_members, c->coop_stride,
+                             c->coop_xcc, c->stream));
       }
     return TTNS_OK;
   }
@@ -2095,10 +2126,10 @@ int ttns_observe(ttns_ctx* c, int32_t kind, int32_t tree, int32_t index, double*
   if (!c || tree < 0 || tree >= (int)c->trees.size() || !host_out)
     return fail(TTNS_EINVAL, "ttns_observe: bad arguments");
   if (c->coop) {  // a timed-out grid barrier invalidates every later result
-    GridBar hb{};
-    HIPCHK(hipMemcpyAsync(&hb, c->d_bar, sizeof hb, hipMemcpyDeviceToHost, c->stream));
+    int abort = 0;
+    HIPCHK(hipMemcpyAsync(&abort, &c->d_bar->abort, sizeof abort, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
-    if (hb.abort) return fail(TTNS_EDEVICE, "cooperative executor: a grid barrier timed out");
+    if (abort) return fail(TTNS_EDEVICE, "cooperative executor: a grid barrier timed out");
   }
   TreeState& t = c->trees[tree];
   HIPCHK(hipStreamSynchronize(c->stream));

@@ -78,7 +78,8 @@ class StarModel(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("krylov_dim", C.c_int32),
                 ("breakdown_tol", C.c_double), ("rank_tol", C.c_double),
-                ("record_capacity", C.c_int32), ("executor", C.c_int32), ("flags", C.c_uint32)]
+                ("record_capacity", C.c_int32), ("executor", C.c_int32), ("flags", C.c_uint32),
+                ("coop_workgroups", C.c_int32)]
 
 
 _lib = None

@@ -126,6 +126,9 @@ def test_rejects_bad_options():
     assert _build_status(t, record_capacity=0) == T.TTNS_EINVAL
     assert _build_status(t, flags=4) == T.TTNS_EINVAL
     assert b"flags" in T.lib().ttns_last_error()
+    assert _build_status(t, coop_workgroups=-1) == T.TTNS_EINVAL
+    assert _build_status(t, coop_workgroups=1025) == T.TTNS_EINVAL
+    assert b"coop_workgroups" in T.lib().ttns_last_error()
 
 
 @pytest.mark.parametrize("model", [W.vibronic_reference(), W.large_tree(), W.vibronic_small()],

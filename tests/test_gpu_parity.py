@@ -97,12 +97,14 @@ def test_autotuned_build_matches_oracle(topology):
     assert_parity(hg, ho)
 
 
+@pytest.mark.parametrize("members", [0, 8, 3])
 @pytest.mark.parametrize("topology", ["star", "er"])
-def test_cooperative_executor_matches_oracle(topology):
-    """All resident workgroups run the step program with grid barriers."""
+def test_cooperative_executor_matches_oracle(topology, members):
+    """The workgroups of one XCD run the step program with barriers in its
+    L2 (default count, 8, and an odd count that leaves ragged shares)."""
     T = _T()
     m = dict(W.vibronic_small(steps=8), topology=topology)
-    (hg,), (st,) = gpu_history([m], m["steps"], executor=T.TTNS_EXEC_COOPERATIVE)
+    (hg,), (st,) = gpu_history([m], m["steps"], executor=T.TTNS_EXEC_COOPERATIVE, coop_workgroups=members)
     _, ho = run(m)
     assert_parity(hg, ho)
     assert st["steps"] == m["steps"]
@@ -110,8 +112,9 @@ def test_cooperative_executor_matches_oracle(topology):
 
 def test_cooperative_executor_equals_wide_at_full_size():
     """Five-level tree at full size, the root on the matrix cores between the
-    cooperative stretches: the same FP64 results as the wide executor (the
-    same partial sums folded in the same order)."""
+    cooperative stretches and the ops too wide for one XCD launched on their
+    own: the same FP64 results as the wide executor (the same partial sums
+    folded in the same order)."""
     T = _T()
     m = W.vibronic_reference()
     (hw,), _ = gpu_history([m], 2, executor=T.TTNS_EXEC_WIDE)
