@@ -40,6 +40,7 @@ constexpr int kMaxContractVb = 64;
 constexpr int kMfmaMinSize = 16384;  // nodes this large use the matrix cores
 constexpr size_t kGraphSegment = 8192;  // launches per captured graph
 constexpr int kQrOneGroupRows = 4096;   // tallest QR left to one workgroup
+constexpr int kSplitLanes = 65536;      // scalar applies spread small nodes over up to this many lanes
 constexpr int kCoopMembers = 32;        // default workgroups of the cooperative executor
 constexpr int kCoopWideVbs = 8;         // ops over more than this many vbs per member run wide
 
@@ -493,7 +494,7 @@ int analyze(TreeState& t, const ttns_opts& o, std::string& err) {
   t.n_el = H.phys[0];
   t.maxC = std::max(t.maxD, t.n_el);
   t.rec_size = 2 * t.n_el * t.n_el + 2 + (int)H.obs_node.size();
-  t.max_nvb = std::max((t.maxsize + kBlock - 1) / kBlock, kMaxContractVb);
+  t.max_nvb = std::max({(t.maxsize + kBlock - 1) / kBlock, kMaxContractVb, kSplitLanes / kBlock});
   return TTNS_OK;
 }
 
@@ -560,6 +561,26 @@ struct Builder {
     return o;
   }
   static int nvb_of(int n) { return (n + kBlock - 1) / kBlock; }
+  // log2 of the lanes per element of a scalar apply over n elements: up to
+  // 8, as long as the grid stays within kSplitLanes lanes
+  static int apply_lg(int n) {
+    int lg = 0;
+    while (lg < 3 && ((size_t)n << (lg + 1)) <= (size_t)kSplitLanes) ++lg;
+    return lg;
+  }
+  static int apply_nvb(int n, int lg) { return (int)((((size_t)n << lg) + kBlock - 1) / kBlock); }
+  // W = H V_j and its dots (mfma: W already produced by the matrix cores)
+  Op lz_op(int v, int j, bool mfma) {
+    const int n = t.shape[v].size;
+    const int lg = mfma ? 0 : apply_lg(n);
+    Op o = base(OP_APPLY_LZ, apply_nvb(n, lg));
+    o.desc = t.heff_desc[v];
+    o.j = j;
+    o.n = n;
+    o.i0 = mfma ? 1 : 0;
+    o.i1 = lg;
+    return o;
+  }
 
   int add_desc(const ApplyDesc& d) {
     c.descs.push_back(d);
@@ -909,8 +930,11 @@ struct Builder {
   }
 
   void apply_op(int desc, const cd* x_override = nullptr) {
-    Op o = base(OP_APPLY, nvb_of(c.descs[desc].sh.size));
+    const int n = c.descs[desc].sh.size;
+    const int lg = apply_lg(n);
+    Op o = base(OP_APPLY, apply_nvb(n, lg));
     o.desc = desc;
+    o.i1 = lg;
     o.p0 = x_override;
     out.push_back(o);
   }
@@ -997,7 +1021,6 @@ struct Builder {
     o.n = n;
     out.push_back(o);
     const int kk = std::min(t.kmax, n);
-    const int hd = t.heff_desc[v];
     const bool mfma = !t.mode_groups[v].empty();
     for (int j = 0; j < kk; ++j) {
       const cd* vj = t.dev.V + (size_t)j * t.dev.ldv;
@@ -1006,12 +1029,7 @@ struct Builder {
       } else {
         for (int p : t.heff_pre[v]) apply_op(p, vj);
       }
-      o = base(OP_APPLY_LZ, nvb_of(n));
-      o.desc = hd;
-      o.j = j;
-      o.n = n;
-      o.i0 = mfma ? 1 : 0;
-      out.push_back(o);
+      out.push_back(lz_op(v, j, mfma));
       o = base(OP_ORTH1, nvb_of(n));
       o.j = j;
       o.n = n;
@@ -1592,7 +1610,10 @@ int validate_program(ttns_ctx& c, const std::vector<Op>& ops, bool allow_user_xy
         const bool user = o.desc >= c.scratch_desc;
         check_desc(rc, a, user || o.p0 != nullptr);
         if (o.p0) rc.in(o.p0, (size_t)a.sh.size * C, "apply input override");
-        if (o.nvb * kBlock < a.sh.size) rc.err = "internal: apply grid too small";
+        if (o.i1 < 0 || o.i1 > 3 || (o.type == OP_APPLY_LZ && o.i0 && o.i1))
+          rc.err = "internal: apply lanes per element";
+        else if ((((size_t)o.nvb * kBlock) >> o.i1) < (size_t)a.sh.size)
+          rc.err = "internal: apply grid too small";
         if (o.type == OP_APPLY_LZ && (o.j < 0 || o.j >= d.kmax || a.sh.size > d.ldv))
           rc.err = "internal: Lanczos index";
         if (o.nvb > t.max_nvb) rc.err = "internal: partial-sum slots";
@@ -1919,14 +1940,7 @@ static int autotune(ttns_ctx& c) {
       const int n = t.shape[v].size;
       const int j = std::min(t.kmax, n) / 2;  // a mid-Lanczos iteration
       const cd* vj = t.dev.V + (size_t)j * t.dev.ldv;
-      auto lz = [&](int mfma) {
-        Op o = b.base(OP_APPLY_LZ, Builder::nvb_of(n));
-        o.desc = t.heff_desc[v];
-        o.j = j;
-        o.n = n;
-        o.i0 = mfma;
-        ops.push_back(o);
-      };
+      auto lz = [&](int mfma) { ops.push_back(b.lz_op(v, j, mfma != 0)); };
       double best = 0.0, ms = 0.0;
       int choice = 0, rc;
       ops.clear();

@@ -82,8 +82,13 @@ __device__ __forceinline__ int coord(const Shape& sh, int idx, int a) {
   return (idx / sh.stride[a]) % sh.dims[a];
 }
 
-// One output element of y = site o x + sum_e coef_e op_e o E_e (src_e).
-__device__ cd apply_point(const ApplyDesc& d, const cd* __restrict__ x, int idx) {
+// One output element of y = site o x + sum_e coef_e op_e o E_e (src_e),
+// computed by the 2^lg consecutive lanes that share idx: lane `sub` takes
+// every 2^lg-th term of each contraction loop, and butterflies add the
+// shares (every lane of the group returns the sum).  Spreading a small node
+// over more lanes shortens each lane's chain of dependent loads.
+__device__ cd apply_point(const ApplyDesc& d, const cd* __restrict__ x, int idx, int sub, int lg) {
+  const int G = 1 << lg;
   const Shape& sh = d.sh;
   const int pa = sh.phys_axis;
   const int dp = sh.dims[pa], sp = sh.stride[pa];
@@ -92,7 +97,7 @@ __device__ cd apply_point(const ApplyDesc& d, const cd* __restrict__ x, int idx)
   if (d.site) {
     const int lo = max(d.site_lo, -s), hi = min(d.site_hi, dp - 1 - s);
     cd part = cz();
-    for (int o = lo; o <= hi; ++o) part = cfma(d.site[s * dp + s + o], x[idx + o * sp], part);
+    for (int o = lo + sub; o <= hi; o += G) part = cfma(d.site[s * dp + s + o], x[idx + o * sp], part);
     acc = cscale(part, d.site_coef);
   }
   for (int k = 0; k < d.n_entries; ++k) {
@@ -104,30 +109,43 @@ __device__ cd apply_point(const ApplyDesc& d, const cd* __restrict__ x, int idx)
     const cd* __restrict__ Erow = e.E + a * D;
     cd part = cz();
     if (!e.op) {
-      for (int b = 0; b < D; ++b) part = cfma(Erow[b], src[base + b * st], part);
+      for (int b = sub; b < D; b += G) part = cfma(Erow[b], src[base + b * st], part);
     } else {
       const int lo = max(e.op_lo, -s), hi = min(e.op_hi, dp - 1 - s);
       for (int o = lo; o <= hi; ++o) {
         const cd oc = e.op[s * dp + s + o];
         const cd* __restrict__ sb = src + base + o * sp;
         cd inner = cz();
-        for (int b = 0; b < D; ++b) inner = cfma(Erow[b], sb[b * st], inner);
+        for (int b = sub; b < D; b += G) inner = cfma(Erow[b], sb[b * st], inner);
         part = cfma(oc, inner, part);
       }
     }
     acc.x = fma(e.coef, part.x, acc.x);
     acc.y = fma(e.coef, part.y, acc.y);
   }
+  for (int off = G >> 1; off > 0; off >>= 1) {
+    acc.x += __shfl_xor(acc.x, off);
+    acc.y += __shfl_xor(acc.y, off);
+  }
   return acc;
 }
 
+// Element and lane of this thread in an apply over 2^lg lanes per element.
+__device__ __forceinline__ int apply_idx(int vb, int lg) { return vb * (kBlock >> lg) + (int)(threadIdx.x >> lg); }
+__device__ __forceinline__ int apply_sub(int lg) { return (int)(threadIdx.x & ((1u << lg) - 1u)); }
+
 // OP_APPLY: desc.y = H x with x = op.p0 when given (Lanczos pre-stages read
-// the current Krylov vector), else desc.x.
+// the current Krylov vector), else desc.x; op.i1 = lg (2^lg lanes per
+// element).
 __device__ void body_apply(const Op& op, const DevTables& T, int vb) {
   const ApplyDesc& d = T.descs[op.desc];
   const cd* x = op.p0 ? op.p0 : d.x;
-  const int idx = vb * kBlock + threadIdx.x;
-  if (idx < d.sh.size) d.y[idx] = apply_point(d, x, idx);
+  const int lg = op.i1;
+  const int idx = apply_idx(vb, lg), sub = apply_sub(lg);
+  if (idx < d.sh.size) {
+    const cd y = apply_point(d, x, idx, sub, lg);
+    if (sub == 0) d.y[idx] = y;
+  }
 }
 
 // ------------------------------------------------------------ Lanczos pieces
@@ -231,17 +249,19 @@ __device__ bool body_apply_lz(const Op& op, const DevTables& T, int vb, Smem& sm
   if (tr.scal->done) return false;
   const ApplyDesc& d = T.descs[op.desc];
   const int n = d.sh.size;
-  const int idx = vb * kBlock + threadIdx.x;
+  const int lg = op.i1;  // 0 when the matrix-core groups produced W
+  const int idx = apply_idx(vb, lg), sub = apply_sub(lg);
   cd w = cz();
   if (idx < n) {
     if (op.i0) {  // W was produced by the matrix-core groups of this apply
       w = tr.W[idx];
     } else {
-      w = apply_point(d, tr.V + (size_t)op.j * tr.ldv, idx);
-      tr.W[idx] = w;
+      w = apply_point(d, tr.V + (size_t)op.j * tr.ldv, idx, sub, lg);
+      if (sub == 0) tr.W[idx] = w;
     }
   }
-  lz_partials(tr, op.j, n, vb, idx, w, sm);
+  // one lane per element enters the dots
+  lz_partials(tr, op.j, n, vb, sub == 0 ? idx : n, sub == 0 ? w : cz(), sm);
   return true;
 }
 __device__ void fin_apply_lz(const Op& op, const DevTables& T, int nvb, Smem& sm) {
