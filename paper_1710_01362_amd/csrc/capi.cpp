@@ -523,7 +523,7 @@ size_t layout_tree(TreeState& t, size_t off, int rec_cap) {
   t.o_qrA = take(ldv * C);
   t.o_qrQ = take(ldv * C);
   t.o_qrv = take(2 * (size_t)t.max_rows * C);
-  t.o_part = take((size_t)t.max_nvb * kRedStride * C);
+  t.o_part = take(2 * (size_t)t.max_nvb * kRedStride * C);  // Lanczos buffers A and B
   t.o_cpart = take((size_t)kMaxContractVb * t.maxC * t.maxC * C);
   t.o_qrpart = take((size_t)kMaxQrVb * kQrStride * C);
   t.o_qrs = take(sizeof(QrScal));
@@ -562,8 +562,11 @@ struct Builder {
   }
   static int nvb_of(int n) { return (n + kBlock - 1) / kBlock; }
   // log2 of the lanes per element of a scalar apply over n elements: up to
-  // 8, as long as the grid stays within kSplitLanes lanes
-  static int apply_lg(int n) {
+  // 8, as long as the grid stays within kSplitLanes lanes.  Only the wide
+  // executor gains: the one-workgroup and one-XCD executors already have
+  // more elements than lanes and would only repeat the dot reductions.
+  int apply_lg(int n) const {
+    if (c.persistent || c.coop) return 0;
     int lg = 0;
     while (lg < 3 && ((size_t)n << (lg + 1)) <= (size_t)kSplitLanes) ++lg;
     return lg;
@@ -579,8 +582,12 @@ struct Builder {
     o.n = n;
     o.i0 = mfma ? 1 : 0;
     o.i1 = lg;
+    o.p1 = part_a();
     return o;
   }
+  // the two partial-dot buffers of the Lanczos ops (max_nvb slots each)
+  cd* part_a() const { return t.dev.partials; }
+  cd* part_b() const { return t.dev.partials + (size_t)t.max_nvb * kRedStride; }
 
   int add_desc(const ApplyDesc& d) {
     c.descs.push_back(d);
@@ -1029,14 +1036,23 @@ struct Builder {
       } else {
         for (int p : t.heff_pre[v]) apply_op(p, vj);
       }
-      out.push_back(lz_op(v, j, mfma));
+      // partial dots: OP_APPLY_LZ -> buffer A -> OP_ORTH1 -> buffer B ->
+      // OP_ORTH2, each consumer folding its producer's partials
+      const Op a = lz_op(v, j, mfma);
+      out.push_back(a);
       o = base(OP_ORTH1, nvb_of(n));
       o.j = j;
       o.n = n;
+      o.p2 = part_a();
+      o.i0 = a.nvb;
+      o.p1 = part_b();
       out.push_back(o);
+      const int nvb1 = o.nvb;
       o = base(OP_ORTH2, nvb_of(n));
       o.j = j;
       o.n = n;
+      o.p2 = part_b();
+      o.i0 = nvb1;
       out.push_back(o);
     }
     o = base(OP_COMBINE, nvb_of(n));
@@ -1617,6 +1633,7 @@ int validate_program(ttns_ctx& c, const std::vector<Op>& ops, bool allow_user_xy
         if (o.type == OP_APPLY_LZ && (o.j < 0 || o.j >= d.kmax || a.sh.size > d.ldv))
           rc.err = "internal: Lanczos index";
         if (o.nvb > t.max_nvb) rc.err = "internal: partial-sum slots";
+        if (o.type == OP_APPLY_LZ) rc.in(o.p1, (size_t)o.nvb * kRedStride * C, "Lanczos partials");
         break;
       }
       case OP_NORM:
@@ -1631,6 +1648,11 @@ int validate_program(ttns_ctx& c, const std::vector<Op>& ops, bool allow_user_xy
       case OP_COMBINE:
         if (o.n > d.ldv || o.nvb * kBlock < o.n || o.nvb > t.max_nvb) rc.err = "internal: vector op size";
         if (o.type == OP_COMBINE) rc.in(o.p1, (size_t)o.n * C, "combine output");
+        if (o.type == OP_ORTH1 || o.type == OP_ORTH2) {
+          if (o.j < 0 || o.j >= d.kmax || o.i0 < 1 || o.i0 > t.max_nvb) rc.err = "internal: Lanczos fold";
+          else rc.in(o.p2, (size_t)o.i0 * kRedStride * C, "Lanczos partials");
+          if (o.type == OP_ORTH1) rc.in(o.p1, (size_t)o.nvb * kRedStride * C, "Lanczos partials");
+        }
         break;
       case OP_COPY:
         rc.in(o.p0, (size_t)o.n * C, "copy source");

@@ -152,7 +152,7 @@ __device__ void body_apply(const Op& op, const DevTables& T, int vb) {
 // Partial sums of conj(V_i) . w (i = 0..j) and |w|^2 of this vb: every
 // thread forms its j+2 products, each wavefront reduces them by butterflies,
 // and the four wavefront sums are added in order.
-__device__ void lz_partials(const TreeDev& tr, int j, int n, int vb, int idx, cd w, Smem& sm) {
+__device__ void lz_partials(const TreeDev& tr, int j, int n, int vb, int idx, cd w, cd* part, Smem& sm) {
   constexpr int kChunk = 6;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int cnt = j + 2;
@@ -183,34 +183,32 @@ __device__ void lz_partials(const TreeDev& tr, int j, int n, int vb, int idx, cd
     cd s = sm.wred[0][threadIdx.x];
 #pragma unroll
     for (int w2 = 1; w2 < kBlock / 64; ++w2) s = cadd(s, sm.wred[w2][threadIdx.x]);
-    tr.partials[vb * kRedStride + threadIdx.x] = s;
+    part[vb * kRedStride + threadIdx.x] = s;
   }
   __syncthreads();
 }
 
-// Fold partial sums into out[0..cnt-1] (the last one into *last when given).
-// Few workgroups: one thread per value, vb order.  Many: every thread sums a
-// strided share of the workgroups, then a fixed-order block reduction.
-__device__ void fold_partials(const TreeDev& tr, int nvb, int cnt, cd* out, double* last, Smem& sm) {
+// Fold the partial sums of the previous Lanczos op (nvb workgroups x cnt
+// values, stride kRedStride) into sm.vec[0..cnt-1].  Every workgroup of the
+// consuming op folds for itself, in the same fixed order (kFoldSeg
+// segments of workgroups summed in parallel, then the segments in order),
+// so no workgroup of the producer waits for the others.
+constexpr int kFoldSeg = kBlock / kRedStride;
+__device__ void lz_fold(const cd* __restrict__ part, int nvb, int cnt, Smem& sm) {
   const int t = threadIdx.x;
-  if (nvb <= 64) {
-    if (t < cnt) {
-      cd s = cz();
-      for (int b = 0; b < nvb; ++b) s = cadd(s, tr.partials[b * kRedStride + t]);
-      if (t == cnt - 1 && last) *last = s.x;
-      else out[t] = s;
-    }
-    return;
-  }
-  for (int i = 0; i < cnt; ++i) {
+  const int seg = t / kRedStride, i = t - seg * kRedStride;
+  if (seg < kFoldSeg && i < cnt) {
     cd s = cz();
-    for (int b = t; b < nvb; b += kBlock) s = cadd(s, tr.partials[b * kRedStride + i]);
-    s = block_sum(s, sm);
-    if (t == 0) {
-      if (i == cnt - 1 && last) *last = s.x;
-      else out[i] = s;
-    }
+    for (int b = seg; b < nvb; b += kFoldSeg) s = cadd(s, part[b * kRedStride + i]);
+    sm.lanes[seg * kRedStride + i] = s;
   }
+  __syncthreads();
+  if (t < cnt) {
+    cd s = sm.lanes[t];
+    for (int g = 1; g < kFoldSeg; ++g) s = cadd(s, sm.lanes[g * kRedStride + t]);
+    sm.vec[t] = s;
+  }
+  __syncthreads();
 }
 
 // OP_NORM: |x| of the vector about to be evolved (op.p0, op.n elements).
@@ -261,76 +259,79 @@ __device__ bool body_apply_lz(const Op& op, const DevTables& T, int vb, Smem& sm
     }
   }
   // one lane per element enters the dots
-  lz_partials(tr, op.j, n, vb, sub == 0 ? idx : n, sub == 0 ? w : cz(), sm);
+  lz_partials(tr, op.j, n, vb, sub == 0 ? idx : n, sub == 0 ? w : cz(), op.p1, sm);
   return true;
-}
-__device__ void fin_apply_lz(const Op& op, const DevTables& T, int nvb, Smem& sm) {
-  const TreeDev& tr = T.trees[op.tree];
-  fold_partials(tr, nvb, op.j + 2, tr.scal->h1, &tr.scal->ww1, sm);
 }
 
 // OP_ORTH1: first classical Gram-Schmidt pass, partial dots of the result.
-__device__ bool body_orth1(const Op& op, const DevTables& T, int vb, Smem& sm) {
+// Prologue (once per workgroup, before its vbs): h1 = V^H W from the
+// partials of OP_APPLY_LZ (op.p2, op.i0 workgroups) into sm.vec; `keep`:
+// this workgroup also stores h1 for alpha_j.
+__device__ void orth1_prologue(const Op& op, const DevTables& T, Smem& sm, bool keep) {
   const TreeDev& tr = T.trees[op.tree];
-  if (tr.scal->done) return false;
+  lz_fold(op.p2, op.i0, op.j + 2, sm);
+  if (keep && (int)threadIdx.x <= op.j) tr.scal->h1[threadIdx.x] = sm.vec[threadIdx.x];
+}
+__device__ void body_orth1(const Op& op, const DevTables& T, int vb, Smem& sm) {
+  const TreeDev& tr = T.trees[op.tree];
   const int n = op.n, j = op.j;
   const int idx = vb * kBlock + threadIdx.x;
   cd w = cz();
   if (idx < n) {
     w = tr.W[idx];
     for (int i = 0; i <= j; ++i) {
-      const cd h = tr.scal->h1[i];
+      const cd h = sm.vec[i];
       const cd v = tr.V[(size_t)i * tr.ldv + idx];
       w = csub(w, make_double2(h.x * v.x - h.y * v.y, h.x * v.y + h.y * v.x));
     }
     tr.W[idx] = w;
   }
-  lz_partials(tr, j, n, vb, idx, w, sm);
-  return true;
-}
-__device__ void fin_orth1(const Op& op, const DevTables& T, int nvb, Smem& sm) {
-  const TreeDev& tr = T.trees[op.tree];
-  fold_partials(tr, nvb, op.j + 2, tr.scal->h2, &tr.scal->ww2, sm);
+  lz_partials(tr, j, n, vb, idx, w, op.p1, sm);
 }
 
-// beta_j from the second pass (same value in every workgroup).
-__device__ double lz_beta(const LzScal* sc, int j) {
-  double b2 = sc->ww2;
-  for (int i = 0; i <= j; ++i) b2 -= cabs2(sc->h2[i]);
+// OP_ORTH2 prologue: h2 = V^H W and |W|^2 after the first pass, from the
+// partials of OP_ORTH1 (op.p2, op.i0 workgroups), into sm.vec.
+__device__ void orth2_prologue(const Op& op, Smem& sm) { lz_fold(op.p2, op.i0, op.j + 2, sm); }
+
+// beta_j from the second pass (same value in every workgroup): |W|^2 after
+// the second subtraction by the norm identity.
+__device__ double lz_beta(const Smem& sm, int j) {
+  double b2 = sm.vec[j + 1].x;
+  for (int i = 0; i <= j; ++i) b2 -= cabs2(sm.vec[i]);
   return sqrt(fmax(b2, 0.0));
+}
+__device__ bool lz_stop(const TreeDev& tr, const Op& op, double beta) {
+  const int j = op.j;
+  return (j == tr.kmax - 1) || (j == op.n - 1) || (beta <= tr.btol * tr.scal->nx);
 }
 
 // OP_ORTH2: second pass, beta_j, V_{j+1} (unless the process stops here).
-__device__ bool body_orth2(const Op& op, const DevTables& T, int vb) {
+__device__ void body_orth2(const Op& op, const DevTables& T, int vb, const Smem& sm) {
   const TreeDev& tr = T.trees[op.tree];
-  const LzScal* sc = tr.scal;
-  if (sc->done) return false;
   const int n = op.n, j = op.j;
-  const double beta = lz_beta(sc, j);
-  const bool stop = (j == tr.kmax - 1) || (j == n - 1) || (beta <= tr.btol * sc->nx);
-  if (stop) return true;
+  const double beta = lz_beta(sm, j);
+  if (lz_stop(tr, op, beta)) return;
   const double ib = 1.0 / beta;
   const int idx = vb * kBlock + threadIdx.x;
   if (idx < n) {
     cd w = tr.W[idx];
     for (int i = 0; i <= j; ++i) {
-      const cd h = sc->h2[i];
+      const cd h = sm.vec[i];
       const cd v = tr.V[(size_t)i * tr.ldv + idx];
       w = csub(w, make_double2(h.x * v.x - h.y * v.y, h.x * v.y + h.y * v.x));
     }
     tr.V[(size_t)(j + 1) * tr.ldv + idx] = cscale(w, ib);
   }
-  return true;
 }
-__device__ void fin_orth2(const Op& op, const DevTables& T) {
+// alpha_j, beta_j and the stop decision (one workgroup).
+__device__ void fin_orth2(const Op& op, const DevTables& T, const Smem& sm) {
   const TreeDev& tr = T.trees[op.tree];
   LzScal* sc = tr.scal;
   if (threadIdx.x == 0) {
     const int j = op.j;
-    const double beta = lz_beta(sc, j);
-    sc->alpha[j] = sc->h1[j].x + sc->h2[j].x;
-    const bool stop = (j == tr.kmax - 1) || (j == op.n - 1) || (beta <= tr.btol * sc->nx);
-    if (stop) {
+    const double beta = lz_beta(sm, j);
+    sc->alpha[j] = sc->h1[j].x + sm.vec[j].x;
+    if (lz_stop(tr, op, beta)) {
       sc->k_eff = j + 1;
       sc->done = 1;
       if (j < tr.kmax - 1 && j < op.n - 1) atomicAdd(&tr.stats[1], 1);
@@ -1234,19 +1235,24 @@ __global__ __launch_bounds__(kBlock) void k_op(Op op, DevTables T) {
   if constexpr (TY == OP_APPLY) {
     body_apply(op, T, vb);
   } else if constexpr (TY == OP_APPLY_LZ) {
-    if (body_apply_lz(op, T, vb, sm) && last_block(tr.counter, op.nvb, sm)) fin_apply_lz(op, T, op.nvb, sm);
+    body_apply_lz(op, T, vb, sm);  // the next op folds the partial dots
   } else if constexpr (TY == OP_NORM) {
     body_norm(op, T, vb, sm);
     if (last_block(tr.counter, op.nvb, sm)) fin_norm(op, T, op.nvb, sm);
   } else if constexpr (TY == OP_SCALE) {
     body_scale(op, T, vb);
   } else if constexpr (TY == OP_ORTH1) {
-    if (body_orth1(op, T, vb, sm) && last_block(tr.counter, op.nvb, sm)) fin_orth1(op, T, op.nvb, sm);
+    if (tr.scal->done) return;
+    orth1_prologue(op, T, sm, vb == 0);
+    body_orth1(op, T, vb, sm);
   } else if constexpr (TY == OP_ORTH2) {
-    // fin_orth2 reads only scalars fixed before this launch (beta comes from
+    // fin_orth2 reads only values fixed before this launch (beta comes from
     // the norm identity of the first pass), so workgroup 0 can run it
     // without waiting for the others: no ticket
-    if (body_orth2(op, T, vb) && vb == 0) fin_orth2(op, T);
+    if (tr.scal->done) return;
+    orth2_prologue(op, sm);
+    body_orth2(op, T, vb, sm);
+    if (vb == 0) fin_orth2(op, T, sm);
   } else if constexpr (TY == OP_COMBINE) {
     body_combine(op, T, vb, sm);
   } else if constexpr (TY == OP_QR) {
@@ -1288,8 +1294,6 @@ __global__ __launch_bounds__(kBlock) void k_persistent(const Op* __restrict__ op
       case OP_APPLY_LZ: {
         bool act = true;
         for (int vb = 0; vb < nvb && act; ++vb) act = body_apply_lz(op, T, vb, sm);
-        __syncthreads();
-        if (act) fin_apply_lz(op, T, nvb, sm);
         break;
       }
       case OP_NORM:
@@ -1300,20 +1304,18 @@ __global__ __launch_bounds__(kBlock) void k_persistent(const Op* __restrict__ op
       case OP_SCALE:
         for (int vb = 0; vb < nvb; ++vb) body_scale(op, T, vb);
         break;
-      case OP_ORTH1: {
-        bool act = true;
-        for (int vb = 0; vb < nvb && act; ++vb) act = body_orth1(op, T, vb, sm);
-        __syncthreads();
-        if (act) fin_orth1(op, T, nvb, sm);
+      case OP_ORTH1:
+        if (T.trees[op.tree].scal->done) break;
+        orth1_prologue(op, T, sm, true);
+        for (int vb = 0; vb < nvb; ++vb) body_orth1(op, T, vb, sm);
         break;
-      }
-      case OP_ORTH2: {
-        bool act = true;
-        for (int vb = 0; vb < nvb && act; ++vb) act = body_orth2(op, T, vb);
+      case OP_ORTH2:
+        if (T.trees[op.tree].scal->done) break;
+        orth2_prologue(op, sm);
+        for (int vb = 0; vb < nvb; ++vb) body_orth2(op, T, vb, sm);
         __syncthreads();
-        if (act) fin_orth2(op, T);
+        fin_orth2(op, T, sm);
         break;
-      }
       case OP_COMBINE:
         for (int vb = 0; vb < nvb; ++vb) body_combine(op, T, vb, sm);
         break;
@@ -1400,7 +1402,9 @@ hipError_t launch_op(const Op& op, const DevTables& t, hipStream_t s) {
 //
 // Within a stretch the virtual workgroups of each op are dealt out
 // round-robin over the members, a barrier separates consecutive ops, and
-// the fold of a reduction op runs in member 0 between two barriers.
+// the fold of a reduction op runs in member 0 between two barriers (the
+// Lanczos ops instead fold their predecessor's partial sums in every member,
+// one barrier per op).
 // One-workgroup ops (QR, bond step, record) run in member 0 while the
 // others wait at the barrier.
 //
@@ -1478,13 +1482,9 @@ __global__ __launch_bounds__(kBlock) void k_coop(const Op* __restrict__ ops, int
       case OP_APPLY:
         for (int vb = b; vb < nvb; vb += G) body_apply(op, T, vb);
         break;
-      case OP_APPLY_LZ: {
-        bool act = true;  // uniform: workgroup 0 always holds virtual workgroup 0
-        for (int vb = b; vb < nvb && act; vb += G) act = body_apply_lz(op, T, vb, sm);
-        grid_sync(bar, gen, (unsigned)G, sm);
-        if (b == 0 && act) fin_apply_lz(op, T, nvb, sm);
+      case OP_APPLY_LZ:  // the next op folds the partial dots in every member
+        for (int vb = b; vb < nvb; vb += G) body_apply_lz(op, T, vb, sm);
         break;
-      }
       case OP_NORM:
         for (int vb = b; vb < nvb; vb += G) body_norm(op, T, vb, sm);
         grid_sync(bar, gen, (unsigned)G, sm);
@@ -1493,20 +1493,15 @@ __global__ __launch_bounds__(kBlock) void k_coop(const Op* __restrict__ ops, int
       case OP_SCALE:
         for (int vb = b; vb < nvb; vb += G) body_scale(op, T, vb);
         break;
-      case OP_ORTH1: {
-        bool act = true;
-        for (int vb = b; vb < nvb && act; vb += G) act = body_orth1(op, T, vb, sm);
-        grid_sync(bar, gen, (unsigned)G, sm);
-        if (b == 0 && act) fin_orth1(op, T, nvb, sm);
+      case OP_ORTH1:
+        orth1_prologue(op, T, sm, b == 0);
+        for (int vb = b; vb < nvb; vb += G) body_orth1(op, T, vb, sm);
         break;
-      }
-      case OP_ORTH2: {
-        bool act = true;
-        for (int vb = b; vb < nvb && act; vb += G) act = body_orth2(op, T, vb);
-        grid_sync(bar, gen, (unsigned)G, sm);
-        if (b == 0 && act) fin_orth2(op, T);
+      case OP_ORTH2:
+        orth2_prologue(op, sm);
+        for (int vb = b; vb < nvb; vb += G) body_orth2(op, T, vb, sm);
+        if (b == 0) fin_orth2(op, T, sm);
         break;
-      }
       case OP_COMBINE:
         for (int vb = b; vb < nvb; vb += G) body_combine(op, T, vb, sm);
         break;
