@@ -51,6 +51,33 @@ __device__ cd block_sum(cd v, Smem& sm) {
   return r;
 }
 
+// Two sums over the workgroup at once (same order as block_sum): returns
+// the sum of a, the sum of b in *bs.
+__device__ cd block_sum2(cd a, cd b, Smem& sm, cd* bs) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    a.x += __shfl_xor(a.x, off);
+    a.y += __shfl_xor(a.y, off);
+    b.x += __shfl_xor(b.x, off);
+    b.y += __shfl_xor(b.y, off);
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    sm.red[wid] = a;
+    sm.wred[wid][0] = b;
+  }
+  __syncthreads();
+  cd ra = sm.red[0], rb = sm.wred[0][0];
+#pragma unroll
+  for (int w = 1; w < kBlock / 64; ++w) {
+    ra = cadd(ra, sm.red[w]);
+    rb = cadd(rb, sm.wred[w][0]);
+  }
+  *bs = rb;
+  return ra;
+}
+
 __device__ double wave_max(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
@@ -199,6 +226,7 @@ __device__ void lz_fold(const cd* __restrict__ part, int nvb, int cnt, Smem& sm)
   const int seg = t / kRedStride, i = t - seg * kRedStride;
   if (seg < kFoldSeg && i < cnt) {
     cd s = cz();
+#pragma unroll 6
     for (int b = seg; b < nvb; b += kFoldSeg) s = cadd(s, part[b * kRedStride + i]);
     sm.lanes[seg * kRedStride + i] = s;
   }
@@ -630,11 +658,14 @@ __device__ void body_qr_t(const Op& op, const DevTables& T, Smem& sm, cd* lds, d
       __syncthreads();
       continue;
     }
-    // completion: first candidate with distance^2 > (rows - k) / (2 rows)
+    // completion: first candidate with distance^2 > (rows - k) / (2 rows),
+    // kBlock candidates per round
     const double thr = 0.5 * (double)(rows - k) / (double)rows;
-    if (threadIdx.x < 64) {
+    {
+      __shared__ int wfirst[kBlock / 64];
+      const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
       int chosen = -1;
-      for (int base = 0; base < rows && chosen < 0; base += 64) {
+      for (int base = 0; base < rows && chosen < 0; base += kBlock) {
         const int n = base + (int)threadIdx.x;
         bool ok = false;
         if (n < rows) {
@@ -656,7 +687,10 @@ __device__ void body_qr_t(const Op& op, const DevTables& T, Smem& sm, cd* lds, d
           ok = (1.0 - w) > thr;
         }
         const unsigned long long m = __ballot(ok);
-        if (m) chosen = base + __ffsll((long long)m) - 1;
+        if (lane == 0) wfirst[wid] = m ? base + wid * 64 + __ffsll((long long)m) - 1 : -1;
+        __syncthreads();
+        for (int w2 = 0; w2 < kBlock / 64 && chosen < 0; ++w2) chosen = wfirst[w2];
+        __syncthreads();
       }
       if (threadIdx.x == 0) sm.ival[2] = chosen < 0 ? -1 : qr_candidate_row(sh, ax, chosen);
     }
@@ -688,21 +722,32 @@ __device__ void body_qr_t(const Op& op, const DevTables& T, Smem& sm, cd* lds, d
       __syncthreads();
       continue;
     }
-    for (int r = threadIdx.x; r < rows; r += kBlock) u[r] = make_double2(r == row ? 1.0 : 0.0, 0.0);
-    __syncthreads();
-    // the projection coefficients of a unit vector are read, not computed,
-    // so one pass leaves u orthogonal to the span to ~k eps / |u|
-    const double iu = 1.0 / sqrt(block_sum(make_double2(qr_subtract(Q, u, rows, k, hb1), 0.0), sm).x);
-    cd rkk = cz();
+    // u = e_row - Q h (the projection coefficients of a unit vector are
+    // read, not computed, so one pass leaves u orthogonal to the span to
+    // ~k eps / |u|); |u|^2 and u^H v in one reduction: q_k = u / |u|,
+    // R_kk = u^H v / |u|
+    double uu = 0.0;
+    cd uv = cz();
+    for (int r = threadIdx.x; r < rows; r += kBlock) {
+      cd a0 = make_double2(r == row ? 1.0 : 0.0, 0.0);
+      for (int j = 0; j < k; ++j) {
+        const cd q0 = Q[(size_t)j * rows + r];
+        const cd h0 = hb1[j];
+        a0 = csub(a0, make_double2(q0.x * h0.x - q0.y * h0.y, q0.x * h0.y + q0.y * h0.x));
+      }
+      u[r] = a0;
+      uu += cabs2(a0);
+      uv = cjfma(a0, v[r], uv);
+    }
+    const cd red = block_sum2(make_double2(uu, 0.0), uv, sm, &uv);
+    const double iu = 1.0 / sqrt(red.x);
     for (int r = threadIdx.x; r < rows; r += kBlock) {
       const cd q = cscale(u[r], iu);
       qk[r] = q;
       if (track) wrow[r] += cabs2(q);
-      rkk = cjfma(q, v[r], rkk);
     }
-    rkk = block_sum(rkk, sm);
     if (threadIdx.x == 0) {
-      R[k * cols + k] = rkk;
+      R[k * cols + k] = cscale(uv, iu);
       atomicAdd(&tr.stats[0], 1);
     }
     __syncthreads();
@@ -1043,8 +1088,8 @@ __device__ void fin_contract(const Op& op, const DevTables& T, int nvb) {
 
 // ------------------------------------------------------------ bond step
 // Y = H_b X for the bond matrix X (Du x Dv), one workgroup; scratch S (Du x Dv).
-// The environment matrices come from `st` (LDS copies laid out as Eu, Ev,
-// then Eu_k, Ev_k per pair) when staged, else from the descriptor.
+// The environment matrices come from `st` (LDS copies laid out as Eu, Ev^T,
+// then Eu_k, Ev_k^T per pair) when staged, else from the descriptor.
 __device__ __forceinline__ const cd* bond_mat(const BondDesc& b, const cd* st, int which, int k) {
   const int u2 = b.Du * b.Du, v2 = b.Dv * b.Dv;
   if (!st) return which == 0 ? (k < 0 ? b.Eu : b.Euk[k]) : (k < 0 ? b.Ev : b.Evk[k]);
@@ -1052,8 +1097,66 @@ __device__ __forceinline__ const cd* bond_mat(const BondDesc& b, const cd* st, i
   return st + (size_t)pair * (u2 + v2) + (which == 0 ? 0 : u2);
 }
 
+// Products of the staged bond step, all operands row-major in LDS, 2 x 2
+// output blocks per thread (each loaded entry feeds two products):
+//   MODE 0: Y = A1 B1 + A2 B2,   MODE 1: Y += coef A1 B1
+// with A1 (Du x K1), B1 (K1 x Dv), A2 (Du x K2), B2 (K2 x Dv), Y (Du x Dv).
+// Rows / columns past the edge of an odd dimension are computed from the
+// last row / column and not stored.  Ends with a barrier.
+template <int MODE>
+__device__ void bond_mm(int Du, int Dv, const cd* A1, const cd* B1, int K1, const cd* A2, const cd* B2, int K2,
+                        cd* Y, double coef) {
+  const int bu = (Du + 1) >> 1, bv = (Dv + 1) >> 1;
+  for (int t = threadIdx.x; t < bu * bv; t += kBlock) {
+    const int a0 = 2 * (t / bv), c0 = 2 * (t % bv);
+    const int a1 = min(a0 + 1, Du - 1), c1 = min(c0 + 1, Dv - 1);
+    cd y00 = cz(), y01 = cz(), y10 = cz(), y11 = cz();
+#pragma unroll 4
+    for (int m = 0; m < K1; ++m) {
+      const cd p0 = A1[a0 * K1 + m], p1 = A1[a1 * K1 + m];
+      const cd q0 = B1[m * Dv + c0], q1 = B1[m * Dv + c1];
+      y00 = cfma(p0, q0, y00);
+      y01 = cfma(p0, q1, y01);
+      y10 = cfma(p1, q0, y10);
+      y11 = cfma(p1, q1, y11);
+    }
+    if (MODE == 0) {
+#pragma unroll 4
+      for (int m = 0; m < K2; ++m) {
+        const cd p0 = A2[a0 * K2 + m], p1 = A2[a1 * K2 + m];
+        const cd q0 = B2[m * Dv + c0], q1 = B2[m * Dv + c1];
+        y00 = cfma(p0, q0, y00);
+        y01 = cfma(p0, q1, y01);
+        y10 = cfma(p1, q0, y10);
+        y11 = cfma(p1, q1, y11);
+      }
+    }
+    auto put = [&](int a, int c, cd v) {
+      cd* o = Y + a * Dv + c;
+      if (MODE == 0) *o = v;
+      else *o = make_double2(fma(coef, v.x, o->x), fma(coef, v.y, o->y));
+    };
+    put(a0, c0, y00);
+    if (c0 + 1 < Dv) put(a0, c0 + 1, y01);
+    if (a0 + 1 < Du) {
+      put(a0 + 1, c0, y10);
+      if (c0 + 1 < Dv) put(a0 + 1, c0 + 1, y11);
+    }
+  }
+  __syncthreads();
+}
+
 __device__ void bond_apply(const BondDesc& b, const cd* st, const cd* X, cd* Y, cd* S) {
   const int Du = b.Du, Dv = b.Dv, n = Du * Dv;
+  if (st) {
+    // staged: Ev and Evk are held transposed, so X Ev^T reads rows of both
+    bond_mm<0>(Du, Dv, bond_mat(b, st, 0, -1), X, Du, X, bond_mat(b, st, 1, -1), Dv, Y, 0.0);
+    for (int k = 0; k < b.n_pairs; ++k) {
+      bond_mm<0>(Du, Dv, X, bond_mat(b, st, 1, k), Dv, nullptr, nullptr, 0, S, 0.0);
+      bond_mm<1>(Du, Dv, bond_mat(b, st, 0, k), S, Du, nullptr, nullptr, 0, Y, b.coef[k]);
+    }
+    return;
+  }
   const cd* Eu = bond_mat(b, st, 0, -1);
   const cd* Ev = bond_mat(b, st, 1, -1);
   for (int p = threadIdx.x; p < n; p += kBlock) {
@@ -1084,6 +1187,24 @@ __device__ void bond_apply(const BondDesc& b, const cd* st, const cd* X, cd* Y, 
   }
 }
 
+// hh[i] = V_i^H W for i < cnt (cnt <= 16; V with leading dimension ld, W of
+// n entries): 16 lanes per dot each sum a strided share, butterflies add the
+// shares; all dots at once, one barrier.
+__device__ void bond_dots(const cd* V, int ld, const cd* W, int n, int cnt, cd* hh) {
+  constexpr int L = kBlock / kMaxKrylov;
+  const int i = threadIdx.x / L, seg = threadIdx.x % L;
+  cd d = cz();
+  if (i < cnt)
+    for (int p = seg; p < n; p += L) d = cjfma(V[(size_t)i * ld + p], W[p], d);
+#pragma unroll
+  for (int off = L >> 1; off > 0; off >>= 1) {
+    d.x += __shfl_xor(d.x, off);
+    d.y += __shfl_xor(d.y, off);
+  }
+  if (i < cnt && seg == 0) hh[i] = d;
+  __syncthreads();
+}
+
 // OP_BOND (one workgroup): R <- exp(sign i h H_b) R by the same Lanczos
 // process as the nodes (CGS2, breakdown, Krylov dimension kmax).  The
 // Krylov basis, work vectors and environment matrices are staged in LDS
@@ -1107,7 +1228,7 @@ __device__ void body_bond_t(const Op& op, const DevTables& T, Smem& sm, cd* lds)
       const cd* su = k < 0 ? b.Eu : b.Euk[k];
       const cd* sv = k < 0 ? b.Ev : b.Evk[k];
       for (int i = threadIdx.x; i < u2; i += kBlock) e[i] = su[i];
-      for (int i = threadIdx.x; i < v2; i += kBlock) e[u2 + i] = sv[i];
+      for (int i = threadIdx.x; i < v2; i += kBlock) e[u2 + (i % b.Dv) * b.Dv + i / b.Dv] = sv[i];  // transposed
       e += u2 + v2;
     }
   }
@@ -1126,13 +1247,7 @@ __device__ void body_bond_t(const Op& op, const DevTables& T, Smem& sm, cd* lds)
     bond_apply(b, st, V + (size_t)j * ld, W, S);
     double a_j = 0.0;
     for (int pass = 0; pass < 2; ++pass) {
-      for (int i = 0; i <= j; ++i) {
-        cd d = cz();
-        for (int p = threadIdx.x; p < n; p += kBlock) d = cjfma(V[(size_t)i * ld + p], W[p], d);
-        d = block_sum(d, sm);
-        if (threadIdx.x == 0) hh[i] = d;
-      }
-      __syncthreads();
+      bond_dots(V, ld, W, n, j + 1, hh);
       for (int p = threadIdx.x; p < n; p += kBlock) {
         cd w = W[p];
         for (int i = 0; i <= j; ++i) {
