@@ -77,6 +77,21 @@ def cpu_baseline(models, seconds=20.0):
                       % (steps, upd, el)}
 
 
+def roctx():
+    """The profiler-control entry points of roctx (pause / resume of a
+    rocprofv3 --selected-regions run), or None without the library."""
+    import ctypes as C
+    for name in ("librocprofiler-sdk-roctx.so.1", "librocprofiler-sdk-roctx.so"):
+        try:
+            L = C.CDLL(name)
+        except OSError:
+            continue
+        L.roctxProfilerPause.argtypes = [C.c_uint64]
+        L.roctxProfilerResume.argtypes = [C.c_uint64]
+        return L
+    return None
+
+
 def roofline_of(kid, k, prec):
     """Bound, achieved and peak of one kernel from its live totals."""
     secs = k["ms"] * 1e-3
@@ -114,6 +129,8 @@ def main():
     ap.add_argument("--executor", default="auto", choices=["auto", "wide", "persistent", "cooperative"])
     ap.add_argument("--coop-workgroups", type=int, default=0,
                     help="workgroups of the cooperative executor (0: library default)")
+    ap.add_argument("--roctx-window", action="store_true",
+                    help="mark the timed and profiled steps as the region a rocprofv3 --selected-regions run records")
     ap.add_argument("--autotune", action="store_true",
                     help="time the H_eff and QR variants at build and plan the fastest")
     args = ap.parse_args()
@@ -153,6 +170,9 @@ def main():
         torch.cuda.synchronize()
         done += n
         print("warm-up: %d/%d steps" % (done, args.warmup), file=sys.stderr, flush=True)
+    rx = roctx() if args.roctx_window else None
+    if rx:
+        rx.roctxProfilerResume(0)
     t0 = time.perf_counter()
     ctx.ttns_tdvp_step(dt, args.steps)
     torch.cuda.synchronize()
@@ -207,9 +227,11 @@ def main():
             out["heff_rooflines"].append(r)
         out["kernel_time_share"] = {kern[k]["name"]: round(kern[k]["ms"] / tot, 4)
                                     for k in sorted(kern, key=lambda k: -kern[k]["ms"])}
+    torch.cuda.synchronize()
+    if rx:
+        rx.roctxProfilerPause(0)
     if args.autotune:
         out["tuning"] = [l for l in ctx.tuning_report().splitlines() if l]
-    torch.cuda.synchronize()
     h = ctx.history(0)
     out["drift"] = {"norm": float(np.abs(h["norm"] - 1).max()),
                     "energy": float(np.abs(h["energy"] - h["energy"][0]).max())}

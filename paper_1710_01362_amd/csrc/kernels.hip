@@ -538,7 +538,7 @@ __device__ double qr_subtract(const cd* Q, cd* v, int rows, int k, const cd* h) 
   return n2;
 }
 
-constexpr int kQrWRows = 768;  // rows whose span weights the QR keeps in LDS (what the LDS budget leaves)
+constexpr int kQrWRows = 640;  // rows whose span weights the QR keeps in LDS (what the LDS budget leaves)
 
 // LDS budget of the QR (complex entries): Q columns plus two row vectors.
 constexpr int kQrLds = kQrLdsEntries;  // 137.5 KiB: a 400 x 20 matrix plus two vectors
@@ -551,7 +551,8 @@ constexpr int kQrLds = kQrLdsEntries;  // 137.5 KiB: a 400 x 20 matrix plus two 
 // orthogonalised twice.  Q and the work vectors live in LDS (`lds`, kQrLds
 // entries) when they fit, else in the tree's global scratch.
 template <bool kLds>
-__device__ void body_qr_t(const Op& op, const DevTables& T, Smem& sm, cd* lds, double* wrow) {
+__device__ void body_qr_t(const Op& op, const DevTables& T, Smem& sm, cd* lds, double* wrow,
+                          unsigned short* ctab) {
   const TreeDev& tr = T.trees[op.tree];
   const Shape& sh = T.descs[op.desc].sh;
   const int ax = op.axis;
@@ -595,7 +596,10 @@ __device__ void body_qr_t(const Op& op, const DevTables& T, Smem& sm, cd* lds, d
   }
   for (int i = threadIdx.x; i < cols * cols; i += kBlock) R[i] = cz();
   if (track)
-    for (int r = threadIdx.x; r < rows; r += kBlock) wrow[r] = 0.0;
+    for (int r = threadIdx.x; r < rows; r += kBlock) {
+      wrow[r] = 0.0;
+      ctab[r] = (unsigned short)qr_candidate_row(sh, ax, r);  // completion order -> row
+    }
   __syncthreads();
   double nrm = 0.0;
   for (int c = 0; c < cols; ++c) nrm += colnrm[c];
@@ -669,7 +673,7 @@ __device__ void body_qr_t(const Op& op, const DevTables& T, Smem& sm, cd* lds, d
         const int n = base + (int)threadIdx.x;
         bool ok = false;
         if (n < rows) {
-          const int row = qr_candidate_row(sh, ax, n);
+          const int row = track ? ctab[n] : qr_candidate_row(sh, ax, n);
           double w;
           if (track) {
             w = wrow[row];
@@ -692,7 +696,8 @@ __device__ void body_qr_t(const Op& op, const DevTables& T, Smem& sm, cd* lds, d
         for (int w2 = 0; w2 < kBlock / 64 && chosen < 0; ++w2) chosen = wfirst[w2];
         __syncthreads();
       }
-      if (threadIdx.x == 0) sm.ival[2] = chosen < 0 ? -1 : qr_candidate_row(sh, ax, chosen);
+      if (threadIdx.x == 0)
+        sm.ival[2] = chosen < 0 ? -1 : track ? ctab[chosen] : qr_candidate_row(sh, ax, chosen);
     }
     __syncthreads();
     const int row = sm.ival[2];
@@ -729,12 +734,21 @@ __device__ void body_qr_t(const Op& op, const DevTables& T, Smem& sm, cd* lds, d
     double uu = 0.0;
     cd uv = cz();
     for (int r = threadIdx.x; r < rows; r += kBlock) {
-      cd a0 = make_double2(r == row ? 1.0 : 0.0, 0.0);
-      for (int j = 0; j < k; ++j) {
+      cd a0 = make_double2(r == row ? 1.0 : 0.0, 0.0), a1 = cz();
+      int j = 0;
+#pragma unroll 2
+      for (; j + 1 < k; j += 2) {
+        const cd q0 = Q[(size_t)j * rows + r], q1 = Q[(size_t)(j + 1) * rows + r];
+        const cd h0 = hb1[j], h1 = hb1[j + 1];
+        a0 = csub(a0, make_double2(q0.x * h0.x - q0.y * h0.y, q0.x * h0.y + q0.y * h0.x));
+        a1 = csub(a1, make_double2(q1.x * h1.x - q1.y * h1.y, q1.x * h1.y + q1.y * h1.x));
+      }
+      if (j < k) {
         const cd q0 = Q[(size_t)j * rows + r];
         const cd h0 = hb1[j];
         a0 = csub(a0, make_double2(q0.x * h0.x - q0.y * h0.y, q0.x * h0.y + q0.y * h0.x));
       }
+      a0 = cadd(a0, a1);
       u[r] = a0;
       uu += cabs2(a0);
       uv = cjfma(a0, v[r], uv);
@@ -759,20 +773,24 @@ __device__ void body_qr_t(const Op& op, const DevTables& T, Smem& sm, cd* lds, d
   }
 }
 
-// kTrack: keep the span weights in LDS (the wide executor's QR kernel); the
-// one-workgroup executors' kernels hold other LDS buffers and do without.
+// kTrack: keep the span weights and the completion-order table in LDS (the
+// wide executor's QR kernel); the one-workgroup executors' kernels hold
+// other LDS buffers and do without.
 template <bool kTrack>
 __device__ void body_qr(const Op& op, const DevTables& T, Smem& sm, cd* lds) {
   const Shape& sh = T.descs[op.desc].sh;
   const int cols = sh.dims[op.axis];
   const int rows = sh.size / cols;
   double* wrow = nullptr;
+  unsigned short* ctab = nullptr;
   if constexpr (kTrack) {
     __shared__ double w[kQrWRows];
+    __shared__ unsigned short ct[kQrWRows];
     wrow = w;
+    ctab = ct;
   }
-  if ((size_t)rows * (cols + 2) <= (size_t)kQrLds) body_qr_t<true>(op, T, sm, lds, wrow);
-  else body_qr_t<false>(op, T, sm, nullptr, wrow);
+  if ((size_t)rows * (cols + 2) <= (size_t)kQrLds) body_qr_t<true>(op, T, sm, lds, wrow, ctab);
+  else body_qr_t<false>(op, T, sm, nullptr, wrow, ctab);
 }
 
 // ------------------------------------------------------------ wide QR
@@ -1073,6 +1091,7 @@ __device__ void fin_contract(const Op& op, const DevTables& T, int nvb) {
   const int D = sh.dims[op.axis];
   for (int p = threadIdx.x; p < D * D; p += kBlock) {
     cd s = cz();
+#pragma unroll 8
     for (int b = 0; b < nvb; ++b) s = cadd(s, tr.cpart[(size_t)b * D * D + p]);
     if (op.i0 == 0) {
       op.p1[p] = s;
