@@ -513,7 +513,8 @@ __device__ void qr_project(const cd* Q, const cd* v, int rows, int k, cd* h) {
 }
 
 // v[r] -= sum_j Q_j[r] h[j]; returns this thread's share of |v|^2.
-__device__ double qr_subtract(const cd* Q, cd* v, int rows, int k, const cd* h) {
+// sync = false: the caller's next step begins with a workgroup barrier.
+__device__ double qr_subtract(const cd* Q, cd* v, int rows, int k, const cd* h, bool sync = true) {
   double n2 = 0.0;
   for (int r = threadIdx.x; r < rows; r += kBlock) {
     cd a0 = v[r], a1 = cz();
@@ -534,7 +535,7 @@ __device__ double qr_subtract(const cd* Q, cd* v, int rows, int k, const cd* h) 
     v[r] = acc;
     n2 += cabs2(acc);
   }
-  __syncthreads();
+  if (sync) __syncthreads();
   return n2;
 }
 
@@ -613,7 +614,23 @@ __device__ void body_qr_t(const Op& op, const DevTables& T, Smem& sm, cd* lds, d
     const int r = threadIdx.x + i * kBlock;
     nxt[i] = r < rows ? A[r] : cz();
   }
+  // a finished column k is written to Q (q_k = v / rn) in the next
+  // iteration's load phase, by the thread owning each row, before that
+  // thread loads the next column into v: one barrier for both
+  int pend_k = -1;
+  double pend_ir = 0.0;
+  auto write_pending = [&]() {
+    if (pend_k < 0) return;
+    cd* qp = Q + (size_t)pend_k * rows;
+    for (int r = threadIdx.x; r < rows; r += kBlock) {
+      const cd q = cscale(v[r], pend_ir);
+      qp[r] = q;
+      if (track) wrow[r] += cabs2(q);
+    }
+    pend_k = -1;
+  };
   for (int k = 0; k < cols; ++k) {
+    write_pending();
 #pragma unroll
     for (int i = 0; i < kPre; ++i) {
       const int r = threadIdx.x + i * kBlock;
@@ -640,26 +657,21 @@ __device__ void body_qr_t(const Op& op, const DevTables& T, Smem& sm, cd* lds, d
       __syncthreads();
     } else if (tiny) {
       qr_project(Q, v, rows, k, hb1);
-      rn = sqrt(block_sum(make_double2(qr_subtract(Q, v, rows, k, hb1), 0.0), sm).x);
+      rn = sqrt(block_sum(make_double2(qr_subtract(Q, v, rows, k, hb1, false), 0.0), sm).x);
       for (int j = threadIdx.x; j < k; j += kBlock) hb2[j] = cz();
       __syncthreads();
     } else {
       qr_project(Q, v, rows, k, hb1);
       qr_subtract(Q, v, rows, k, hb1);
       qr_project(Q, v, rows, k, hb2);
-      rn = sqrt(block_sum(make_double2(qr_subtract(Q, v, rows, k, hb2), 0.0), sm).x);
+      rn = sqrt(block_sum(make_double2(qr_subtract(Q, v, rows, k, hb2, false), 0.0), sm).x);
     }
     for (int j = threadIdx.x; j < k; j += kBlock) R[j * cols + k] = cadd(hb1[j], hb2[j]);
     cd* qk = Q + (size_t)k * rows;
     if (rn > tol) {
-      const double ir = 1.0 / rn;
-      for (int r = threadIdx.x; r < rows; r += kBlock) {
-        const cd q = cscale(v[r], ir);
-        qk[r] = q;
-        if (track) wrow[r] += cabs2(q);
-      }
       if (threadIdx.x == 0) R[k * cols + k] = make_double2(rn, 0.0);
-      __syncthreads();
+      pend_k = k;
+      pend_ir = 1.0 / rn;
       continue;
     }
     // completion: first candidate with distance^2 > (rows - k) / (2 rows),
@@ -766,6 +778,8 @@ __device__ void body_qr_t(const Op& op, const DevTables& T, Smem& sm, cd* lds, d
     }
     __syncthreads();
   }
+  write_pending();
+  __syncthreads();
   // scatter Q back into the node tensor
   for (int r = threadIdx.x; r < rows; r += kBlock) {
     const int off = qr_row_offset(sh, ax, r);
