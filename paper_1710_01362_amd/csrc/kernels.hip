@@ -1179,8 +1179,77 @@ __device__ void bond_mm(int Du, int Dv, const cd* A1, const cd* B1, int K1, cons
   __syncthreads();
 }
 
-__device__ void bond_apply(const BondDesc& b, const cd* st, const cd* X, cd* Y, cd* S) {
+// Every pair at once (S holds n_pairs scratch matrices): S_k = X Ev_k^T for
+// all k in one pass, then Y += sum_k coef_k Eu_k S_k in one pass, adding
+// the pairs in order as the one-pair-at-a-time form does.
+__device__ void bond_pairs(const BondDesc& b, const cd* st, const cd* X, cd* Y, cd* S) {
+  const int Du = b.Du, Dv = b.Dv, n = Du * Dv, np = b.n_pairs;
+  const int bu = (Du + 1) >> 1, bv = (Dv + 1) >> 1;
+  for (int t = threadIdx.x; t < bu * bv * np; t += kBlock) {
+    const int k = t / (bu * bv), tb = t - k * bu * bv;
+    const int a0 = 2 * (tb / bv), c0 = 2 * (tb % bv);
+    const int a1 = min(a0 + 1, Du - 1), c1 = min(c0 + 1, Dv - 1);
+    const cd* B = bond_mat(b, st, 1, k);
+    cd y00 = cz(), y01 = cz(), y10 = cz(), y11 = cz();
+#pragma unroll 4
+    for (int m = 0; m < Dv; ++m) {
+      const cd p0 = X[a0 * Dv + m], p1 = X[a1 * Dv + m];
+      const cd q0 = B[m * Dv + c0], q1 = B[m * Dv + c1];
+      y00 = cfma(p0, q0, y00);
+      y01 = cfma(p0, q1, y01);
+      y10 = cfma(p1, q0, y10);
+      y11 = cfma(p1, q1, y11);
+    }
+    cd* o = S + (size_t)k * n;
+    o[a0 * Dv + c0] = y00;
+    if (c0 + 1 < Dv) o[a0 * Dv + c0 + 1] = y01;
+    if (a0 + 1 < Du) {
+      o[(a0 + 1) * Dv + c0] = y10;
+      if (c0 + 1 < Dv) o[(a0 + 1) * Dv + c0 + 1] = y11;
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < bu * bv; t += kBlock) {
+    const int a0 = 2 * (t / bv), c0 = 2 * (t % bv);
+    const int a1 = min(a0 + 1, Du - 1), c1 = min(c0 + 1, Dv - 1);
+    cd y00 = Y[a0 * Dv + c0], y01 = Y[a0 * Dv + c1], y10 = Y[a1 * Dv + c0], y11 = Y[a1 * Dv + c1];
+    for (int k = 0; k < np; ++k) {
+      const cd* A = bond_mat(b, st, 0, k);
+      const cd* Sk = S + (size_t)k * n;
+      cd p00 = cz(), p01 = cz(), p10 = cz(), p11 = cz();
+#pragma unroll 4
+      for (int m = 0; m < Du; ++m) {
+        const cd e0 = A[a0 * Du + m], e1 = A[a1 * Du + m];
+        const cd q0 = Sk[m * Dv + c0], q1 = Sk[m * Dv + c1];
+        p00 = cfma(e0, q0, p00);
+        p01 = cfma(e0, q1, p01);
+        p10 = cfma(e1, q0, p10);
+        p11 = cfma(e1, q1, p11);
+      }
+      const double c = b.coef[k];
+      y00 = make_double2(fma(c, p00.x, y00.x), fma(c, p00.y, y00.y));
+      y01 = make_double2(fma(c, p01.x, y01.x), fma(c, p01.y, y01.y));
+      y10 = make_double2(fma(c, p10.x, y10.x), fma(c, p10.y, y10.y));
+      y11 = make_double2(fma(c, p11.x, y11.x), fma(c, p11.y, y11.y));
+    }
+    Y[a0 * Dv + c0] = y00;
+    if (c0 + 1 < Dv) Y[a0 * Dv + c0 + 1] = y01;
+    if (a0 + 1 < Du) {
+      Y[(a0 + 1) * Dv + c0] = y10;
+      if (c0 + 1 < Dv) Y[(a0 + 1) * Dv + c0 + 1] = y11;
+    }
+  }
+  __syncthreads();
+}
+
+// all_pairs: S has room for n_pairs matrices (bond_pairs), else one.
+__device__ void bond_apply(const BondDesc& b, const cd* st, const cd* X, cd* Y, cd* S, bool all_pairs) {
   const int Du = b.Du, Dv = b.Dv, n = Du * Dv;
+  if (st && all_pairs) {
+    bond_mm<0>(Du, Dv, bond_mat(b, st, 0, -1), X, Du, X, bond_mat(b, st, 1, -1), Dv, Y, 0.0);
+    if (b.n_pairs > 0) bond_pairs(b, st, X, Y, S);
+    return;
+  }
   if (st) {
     // staged: Ev and Evk are held transposed, so X Ev^T reads rows of both
     bond_mm<0>(Du, Dv, bond_mat(b, st, 0, -1), X, Du, X, bond_mat(b, st, 1, -1), Dv, Y, 0.0);
@@ -1238,6 +1307,13 @@ __device__ void bond_dots(const cd* V, int ld, const cd* W, int n, int cnt, cd* 
   __syncthreads();
 }
 
+// LDS entries of a staged bond step: Krylov basis, W, `scratch` matrices
+// and the environment matrices.
+__device__ size_t bond_lds_need(const BondDesc& b, int kmax, int scratch) {
+  const size_t n = (size_t)b.Du * b.Dv;
+  return (kmax + 2 + scratch) * n + (size_t)(1 + b.n_pairs) * (b.Du * b.Du + b.Dv * b.Dv);
+}
+
 // OP_BOND (one workgroup): R <- exp(sign i h H_b) R by the same Lanczos
 // process as the nodes (CGS2, breakdown, Krylov dimension kmax).  The
 // Krylov basis, work vectors and environment matrices are staged in LDS
@@ -1252,9 +1328,11 @@ __device__ void body_bond_t(const Op& op, const DevTables& T, Smem& sm, cd* lds)
   cd* V = kLds ? lds : tr.bondV;
   cd* W = kLds ? lds + (size_t)(kmax + 1) * n : tr.bondW;
   cd* S = kLds ? W + n : tr.bondW + op.i0;
+  // room in LDS for one scratch matrix per pair
+  const bool all_pairs = kLds && bond_lds_need(b, kmax, max(b.n_pairs, 1)) <= (size_t)kQrLds;
   const cd* st = nullptr;
   if (kLds) {
-    cd* e = S + n;
+    cd* e = S + (size_t)(all_pairs ? max(b.n_pairs, 1) : 1) * n;
     st = e;
     const int u2 = b.Du * b.Du, v2 = b.Dv * b.Dv;
     for (int k = -1; k < b.n_pairs; ++k) {
@@ -1277,7 +1355,7 @@ __device__ void body_bond_t(const Op& op, const DevTables& T, Smem& sm, cd* lds)
   __syncthreads();
   int k = 0;
   for (int j = 0; j < kmax; ++j) {
-    bond_apply(b, st, V + (size_t)j * ld, W, S);
+    bond_apply(b, st, V + (size_t)j * ld, W, S, all_pairs);
     double a_j = 0.0;
     for (int pass = 0; pass < 2; ++pass) {
       bond_dots(V, ld, W, n, j + 1, hh);
@@ -1323,8 +1401,7 @@ __device__ void body_bond(const Op& op, const DevTables& T, Smem& sm, cd* lds) {
   const BondDesc& b = T.bonds[op.desc];
   const int n = b.Du * b.Dv;
   const int kmax = min(tr.kmax, n);
-  const size_t need = (size_t)(kmax + 3) * n + (size_t)(1 + b.n_pairs) * (b.Du * b.Du + b.Dv * b.Dv);
-  if (need <= (size_t)kQrLds) body_bond_t<true>(op, T, sm, lds);
+  if (bond_lds_need(b, kmax, 1) <= (size_t)kQrLds) body_bond_t<true>(op, T, sm, lds);
   else body_bond_t<false>(op, T, sm, nullptr);
 }
 
