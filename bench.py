@@ -8,16 +8,18 @@ and the observables of the step), i.e. 2 * n_nodes site updates per tree.
 
 Default workload: the five-level vibronic tree (4 chains x 40 sites, local
 dimension 20, bond dimension 20, dt = 0.5 fs), synthetic seeded parameters,
-FP64.  Timed region: K graph-replayed steps with the inputs resident in HBM.
-The cost of a step grows along a trajectory (the Lanczos processes of chain
-sites still in their vacuum stop after one iteration early on), so by default
-the timed window sits in the middle of the workload's job (steps 185-215 of
-the 400-step vibronic run) after W untimed steps.
-The per-kernel figures come from extra profiled steps of the same run (one
-launch at a time, HIP events around each launch on the library's stream).
+FP64.  The cost of a step grows along a trajectory (the Lanczos processes of
+chain sites still in their vacuum stop after one iteration early on), so the
+benchmark runs the workload's whole job from t = 0 and times K of its steps
+spread evenly over it (step floor(i * job / K) for i < K), each bracketed by
+device synchronisations, with the inputs resident in HBM: their mean is the
+job's mean step time.  W warm-up steps run first on a separate context.  The
+per-kernel figures come from a few profiled steps spread over the job (one
+launch at a time, HIP events around each launch on the library's stream);
+the trajectory is compared with the oracle's stored one where it exists.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
-                    [--precision fp64|fp32|bf16x3]
+                    [--precision fp64|fp32|bf16x3] [--job STEPS]
 """
 import argparse
 import json
@@ -48,10 +50,10 @@ WORKLOADS = {
                  "launch per step, seed 3"),
 }
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
-# default (warmup, steps) per workload and the length of its job: a window in
-# the middle of the job where that is affordable
-WINDOW = {"vibronic": (185, 30, 400), "spin_boson": (85, 30, 200), "large_er": (0, 1, 200),
-          "ensemble": (2, 5, 100)}
+# length of each workload's job (steps from t = 0)
+JOB = {"vibronic": 400, "spin_boson": 200, "large_er": 200, "ensemble": 100}
+# the oracle's stored trajectory of a workload (tests/golden)
+GOLDEN = {"vibronic": "five_level_tree_fp64_400.npz"}
 
 
 def cpu_baseline(models, seconds=20.0):
@@ -75,21 +77,6 @@ def cpu_baseline(models, seconds=20.0):
     return {"value": upd / el, "unit": "site updates/s", "cores": int(threads), "kind": "oracle",
             "sample": "%d full TDVP step(s) of tree 0 of the same workload (%d site updates) in %.1f s"
                       % (steps, upd, el)}
-
-
-def roctx():
-    """The profiler-control entry points of roctx (pause / resume of a
-    rocprofv3 --selected-regions run), or None without the library."""
-    import ctypes as C
-    for name in ("librocprofiler-sdk-roctx.so.1", "librocprofiler-sdk-roctx.so"):
-        try:
-            L = C.CDLL(name)
-        except OSError:
-            continue
-        L.roctxProfilerPause.argtypes = [C.c_uint64]
-        L.roctxProfilerResume.argtypes = [C.c_uint64]
-        return L
-    return None
 
 
 def roofline_of(kid, k, prec):
@@ -116,21 +103,34 @@ def roofline_of(kid, k, prec):
             "bytes_per_launch": by / k["launches"], "share_of_step_time": None}
 
 
+def sample_positions(job, k):
+    """Job step (0-based) of each of the k timed steps: spread evenly over
+    the job; beyond one job's length, whole further jobs from t = 0."""
+    if k <= job:
+        return [(i * job) // k for i in range(k)]
+    return [i % job for i in range(k)]
+
+
+def pop_error(hist, golden_path, n):
+    """Largest |P_j(t_k) - P_j^oracle(t_k)| over the first n records."""
+    g = np.load(golden_path, allow_pickle=False)
+    pg = np.einsum("kjj->kj", hist["rdm"][:n]).real
+    po = np.einsum("kjj->kj", g["rdm"][:n]).real
+    return float(np.abs(pg - po).max())
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: per workload)")
-    ap.add_argument("--warmup", type=int, default=None, help="untimed steps first (default: per workload)")
+    ap.add_argument("--steps", type=int, default=20, help="timed steps, spread over the job")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed steps on a separate context first")
     ap.add_argument("--workload", default="vibronic", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp64", choices=sorted(PREC))
-    ap.add_argument("--profile-steps", type=int, default=2)
+    ap.add_argument("--job", type=int, default=None, help="job length in steps (default: the workload's)")
+    ap.add_argument("--profile-steps", type=int, default=4)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--executor", default="auto", choices=["auto", "wide", "persistent", "cooperative"])
-    ap.add_argument("--coop-workgroups", type=int, default=0,
-                    help="workgroups of the cooperative executor (0: library default)")
-    ap.add_argument("--roctx-window", action="store_true",
-                    help="mark the timed and profiled steps as the region a rocprofv3 --selected-regions run records")
+    ap.add_argument("--executor", default="auto", choices=["auto", "wide", "persistent"])
     ap.add_argument("--autotune", action="store_true",
                     help="time the H_eff and QR variants at build and plan the fastest")
     args = ap.parse_args()
@@ -143,41 +143,62 @@ def main():
     from paper_1710_01362_amd import ttns as T
 
     make, desc = WORKLOADS[args.workload]
-    dw, ds, job = WINDOW[args.workload]
-    if args.warmup is None:
-        args.warmup = dw
-    if args.steps is None:
-        args.steps = ds
+    job = args.job if args.job is not None else JOB[args.workload]
     models = make()
     upd_per_step = sum(2 * W.node_count(m) for m in models)
-    total = args.warmup + args.steps + args.profile_steps + 1
     flags = T.TTNS_FLAG_AUTOTUNE if args.autotune else 0
-    t_build = time.perf_counter()
-    ex = {"auto": T.TTNS_EXEC_AUTO, "wide": T.TTNS_EXEC_WIDE, "persistent": T.TTNS_EXEC_PERSISTENT,
-          "cooperative": T.TTNS_EXEC_COOPERATIVE}[args.executor]
-    ctx = T.Context(models, opts=T.default_opts(record_capacity=total + 1, executor=ex,
-                                                precision=PREC[args.precision], flags=flags,
-                                                coop_workgroups=args.coop_workgroups))
-    torch.cuda.synchronize()
-    t_build = time.perf_counter() - t_build
-    dt = models[0]["dt"]
+    ex = {"auto": T.TTNS_EXEC_AUTO, "wide": T.TTNS_EXEC_WIDE, "persistent": T.TTNS_EXEC_PERSISTENT}[args.executor]
     persistent = args.executor == "persistent" or (args.executor == "auto" and len(models) > 1)
+    dt = models[0]["dt"]
+    opts = dict(record_capacity=job + 1, executor=ex, precision=PREC[args.precision], flags=flags)
 
-    done = 0
-    while done < args.warmup:  # in chunks, with a progress line on stderr
-        n = min(50, args.warmup - done)
-        ctx.ttns_tdvp_step(dt, n)
+    if args.warmup > 0:  # code loading, graph instantiation, caches
+        wctx = T.Context(models, opts=T.default_opts(**opts))
+        for i in range(args.warmup):
+            wctx.ttns_tdvp_step(dt, 1)
+            torch.cuda.synchronize()
+        wctx.close()
+        print("warm-up: %d steps" % args.warmup, file=sys.stderr, flush=True)
+
+    timed = sample_positions(job, args.steps)
+    n_jobs = (args.steps + job - 1) // job
+    n_prof = 0 if persistent else min(args.profile_steps, job)
+    # profiled steps sit between the timed ones (first job only)
+    prof_at = sorted(set(((2 * i + 1) * job) // (2 * n_prof) for i in range(n_prof)) - set(timed))
+    el = 0.0
+    t_build = 0.0
+    kern = None
+    hist = None
+    step_flops = 0.0
+    for jn in range(n_jobs):
+        tb = time.perf_counter()
+        ctx = T.Context(models, opts=T.default_opts(**opts))
         torch.cuda.synchronize()
-        done += n
-        print("warm-up: %d/%d steps" % (done, args.warmup), file=sys.stderr, flush=True)
-    rx = roctx() if args.roctx_window else None
-    if rx:
-        rx.roctxProfilerResume(0)
-    t0 = time.perf_counter()
-    ctx.ttns_tdvp_step(dt, args.steps)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    step_flops = sum(ctx.step_flops(i)[0] for i in range(len(models)))
+        t_build = time.perf_counter() - tb
+        step_flops = sum(ctx.step_flops(i)[0] for i in range(len(models)))
+        mine = [p for i, p in enumerate(timed) if i // job == jn] if args.steps > job else timed
+        last = job - 1 if jn == 0 else max(mine)  # the first job runs to its end
+        for pos in range(last + 1):
+            if pos in mine:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ctx.ttns_tdvp_step(dt, 1)
+                torch.cuda.synchronize()
+                el += time.perf_counter() - t0
+            elif jn == 0 and pos in prof_at:
+                ctx.profile(True)
+                ctx.ttns_tdvp_step(dt, 1)
+                ctx.profile(False)
+            else:
+                ctx.ttns_tdvp_step(dt, 1)
+            if (pos + 1) % 50 == 0:
+                torch.cuda.synchronize()
+                print("job %d: step %d/%d" % (jn, pos + 1, last + 1), file=sys.stderr, flush=True)
+        if jn == 0:
+            if n_prof:
+                kern = ctx.profile_kernels()
+            hist = [ctx.history(i) for i in range(len(models))]
+        ctx.close()
 
     out = {
         "metric": "TDVP site updates/s + % MFMA peak vs FP64 plain at ≤1e-6 population error",
@@ -196,12 +217,11 @@ def main():
         "config": {"workload": desc, "trees": len(models), "site_updates_per_step": upd_per_step,
                    "krylov": models[0]["krylov"],
                    "executor": "one persistent workgroup per tree" if persistent
-                   else ("the workgroups of one XCD per operation, barriers in its L2, one cooperative "
-                         "launch per stretch"
-                         if args.executor == "cooperative"
-                         else "one kernel per operation, replayed as a HIP graph"),
+                   else "one kernel per operation, replayed as HIP graphs",
                    "autotuned": bool(args.autotune), "build_s": round(t_build, 2),
-                   "window": "steps %d-%d of the %d-step job" % (args.warmup, args.warmup + args.steps, job)},
+                   "window": "%d steps spread evenly over the %d-step job from t = 0 (steps %s)"
+                             % (args.steps, job, ",".join(str(p) for p in timed[:8])
+                                + (",..." if len(timed) > 8 else ""))},
         "step_tflops": step_flops / (el / args.steps) / 1e12,
     }
     if persistent:
@@ -210,15 +230,12 @@ def main():
                            "achieved": out["step_tflops"], "peak": PEAK["fp64"], "unit": "TFLOP/s",
                            "frac": out["step_tflops"] / PEAK["fp64"], "traffic": None,
                            "avg_launch_ms": out["ms_per_step"], "flops_per_launch": step_flops}
-    else:
-        ctx.profile(True)
-        ctx.ttns_tdvp_step(dt, args.profile_steps)
-        kern = ctx.profile_kernels()
-        ctx.profile(False)
+    elif kern:
         tot = sum(k["ms"] for k in kern.values())
         dom = max(kern, key=lambda k: kern[k]["ms"])
         out["roofline"] = roofline_of(dom, kern[dom], args.precision)
         out["roofline"]["share_of_step_time"] = kern[dom]["ms"] / tot
+        out["roofline"]["profiled_steps"] = prof_at
         heff = [kid for kid in (1, 16, 17, 18) if kid in kern]
         out["heff_rooflines"] = []
         for kid in heff:
@@ -227,15 +244,16 @@ def main():
             out["heff_rooflines"].append(r)
         out["kernel_time_share"] = {kern[k]["name"]: round(kern[k]["ms"] / tot, 4)
                                     for k in sorted(kern, key=lambda k: -kern[k]["ms"])}
-    torch.cuda.synchronize()
-    if rx:
-        rx.roctxProfilerPause(0)
-    if args.autotune:
-        out["tuning"] = [l for l in ctx.tuning_report().splitlines() if l]
-    h = ctx.history(0)
+    h = hist[0]
     out["drift"] = {"norm": float(np.abs(h["norm"] - 1).max()),
-                    "energy": float(np.abs(h["energy"] - h["energy"][0]).max())}
-    ctx.close()
+                    "energy": float(np.abs(h["energy"] - h["energy"][0]).max()),
+                    "records": int(len(h["norm"]))}
+    gname = GOLDEN.get(args.workload)
+    gpath = os.path.join(ROOT, "tests", "golden", gname) if gname else None
+    if gpath and os.path.exists(gpath):
+        n = len(h["norm"])
+        out["pop_error_vs_oracle"] = {"value": pop_error(h, gpath, n), "records": n,
+                                      "reference": "tests/golden/" + gname}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(models, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -36,7 +36,7 @@
  * row-major) then b (out); with the skip, W_s (n^2 x input, row-major) last.
  *
  * Conventions shared with ttns.h: calls return TTNS_OK or a negative
- * TTNS_E* code and never abort; ttns_last_error() gives the calling thread's
+ * TTNS_E* code and never abort; ttns_last_error(NULL) gives the calling thread's
  * message.  Device pointers are HIP device addresses on the device that is
  * current when ttnn_build is called; all work is enqueued on the stream
  * given to ttnn_build.  Calls that return host data synchronise that stream.

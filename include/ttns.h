@@ -22,7 +22,8 @@
  *   - Node tensor axes: [bond to parent] (absent at the root), physical leg,
  *     bonds to the children in child order; row-major, last axis fastest.
  *   - Every call returns a status: TTNS_OK or a negative code.  No call
- *     aborts; ttns_last_error() returns a message for the calling thread.
+ *     aborts; ttns_last_error(ctx) returns the message of the context's last
+ *     failure (ttns_last_error(NULL): the calling thread's).
  *   - Device pointers ("dev_") are HIP device addresses; host pointers are
  *     ordinary memory.  The caller owns every buffer it passes; the library
  *     copies host inputs during the call and never frees caller memory.
@@ -44,7 +45,11 @@ extern "C" {
 #define TTNS_EINVAL (-1)   /* invalid argument, topology or Hamiltonian   */
 #define TTNS_ENOMEM (-2)   /* workspace too small                          */
 #define TTNS_EDEVICE (-3)  /* a HIP call failed                             */
-#define TTNS_ENUMERIC (-4) /* NaN/Inf or norm watchdog tripped             */
+#define TTNS_ENUMERIC (-4) /* non-finite values: at build, in the inputs; at
+                              run time, a non-finite record (norm, energy,
+                              density matrix) or a QR that found no
+                              completion vector, reported by the next
+                              ttns_observe of that tree                    */
 
 /* arithmetic of the H_eff contractions (Lanczos, exponentials, QR and the
  * environments always run in FP64) */
@@ -56,16 +61,6 @@ extern "C" {
 #define TTNS_EXEC_AUTO 0
 #define TTNS_EXEC_WIDE 1       /* each operation spread over many workgroups */
 #define TTNS_EXEC_PERSISTENT 2 /* one workgroup runs a whole tree's step     */
-#define TTNS_EXEC_COOPERATIVE 3 /* the workgroups of ONE XCD run stretches of
-                                   the step program together, a barrier
-                                   between operations (no L2 write-back:
-                                   the members share that XCD's L2); ops
-                                   too wide for one XCD and the matrix-core
-                                   groups are launched on their own, one
-                                   cooperative launch per stretch between
-                                   them.  Refused (TTNS_EDEVICE) where the
-                                   dispatcher does not deal workgroups
-                                   round-robin over the XCDs.            */
 
 /* option flags */
 #define TTNS_FLAG_MFMA_ALL 1u  /* matrix-core H_eff for every node whose bonds
@@ -177,43 +172,88 @@ typedef struct ttns_ctx ttns_ctx;
 /* Fill opts with the defaults named above. */
 void ttns_default_opts(ttns_opts *opts);
 
-/* Chain mapping (closed form of the hard-cutoff power-law density, Chin et
- * al. 2010 as cited by the paper): c0, eps[0..L-1], hop[0..L-2]. */
+/* Chain mapping of one environment (Methods, "Tensor Network States", and
+ * "Interface to TTNS": the orthogonal-polynomial chain transformation of
+ * Chin et al. 2010 that the paper cites), closed form of the hard-cutoff
+ * power-law density J(w) = 2 pi alpha wc (w/wc)^s theta(wc - w):
+ *   c0 = coupling of the system to site 0 (the reaction coordinate of
+ *        Eq. (2)), eps[0..L-1] = site energies, hop[0..L-2] = hoppings.
+ * Host pointers owned by the caller (hop may be NULL for L = 1).
+ * TTNS_EINVAL for L < 1, wc <= 0, s <= -1, alpha < 0 or a NULL output. */
 int ttns_ohmic_chain(double alpha, double wc, double s, int32_t L, double *c0,
                      double *eps, double *hop);
 
-/* Device bytes ttns_build needs for these trees (all trees run together). */
+/* Device bytes ttns_build (ttns_star_build) needs for these trees, all trees
+ * run together.  The trees are validated as by the build; *bytes receives
+ * the size (host pointer).  TTNS_EINVAL / TTNS_ENUMERIC as for the build. */
 int ttns_workspace_size(const ttns_tree *trees, int32_t n_trees,
                         const ttns_opts *opts, size_t *bytes);
 int ttns_star_workspace_size(const ttns_star_model *models, int32_t n_models,
                              const ttns_opts *opts, size_t *bytes);
 
-/* Validate, lay out the workspace, upload operators, initialise the padded
- * product state and build every environment towards the root.  dev_ws must
- * hold ws_bytes >= ttns_workspace_size(...) bytes, 256-byte aligned; it is
- * used until ttns_destroy.  hip_stream (hipStream_t, may be NULL for the
- * default stream) orders all device work of this context.  Records t = 0. */
+/* Build the TTNS of every tree (section "TTNS for vibronic quantum dynamics":
+ * one tensor per node, bond dimension D per edge; the star form of Eq. (2)
+ * or, with ER nodes, the tree of Fig. 2): validate the topology and the
+ * Hermiticity of the operator sum, lay out the workspace, upload the
+ * operators, initialise the product state (electronic level(s) given,
+ * environments in their vacuum: the zero-temperature start of Methods) with
+ * every non-root node an isometry towards the root, and build every
+ * environment towards the root.
+ *   trees / models: host descriptions, copied during the call.
+ *   dev_ws: device memory of ws_bytes >= the size query, 256-byte aligned,
+ *           owned by the caller and used by the context until ttns_destroy
+ *           (the library never allocates device memory).
+ *   hip_stream: hipStream_t (NULL: the default stream) that orders all device
+ *           work of the context.
+ *   *out: the new context (NULL on failure).  Records t = 0.
+ * Errors: TTNS_EINVAL (topology, dims, operators, non-Hermitian sum, bond
+ * dimension above 64, options), TTNS_ENUMERIC (non-finite inputs),
+ * TTNS_ENOMEM (workspace too small), TTNS_EDEVICE (a HIP call failed). */
 int ttns_build(const ttns_tree *trees, int32_t n_trees, const ttns_opts *opts,
                void *dev_ws, size_t ws_bytes, void *hip_stream, ttns_ctx **out);
 int ttns_star_build(const ttns_star_model *models, int32_t n_models,
                     const ttns_opts *opts, void *dev_ws, size_t ws_bytes,
                     void *hip_stream, ttns_ctx **out);
 
-/* Move the orthogonality centre of `tree` to `node` (QR + environment
- * updates, a gauge change only), then dev_out = H_eff(node) dev_in, where
- * dev_in/dev_out hold one node tensor (complex, node tensor layout).  The
- * centre stays at `node`; the next ttns_tdvp_step moves it back to the root.
- * Asynchronous on the context's stream. */
+/* The local effective Hamiltonian of one node, H_eff(t) of the section "TTNS
+ * for vibronic quantum dynamics" (every tensor is evolved with an H_eff built
+ * from the full many-body state; the same operator whose eigenvalues give the
+ * energy surfaces of Eqs. (3)-(4) at the root).  First moves the
+ * orthogonality centre of `tree` to `node` (QR + environment updates: a
+ * gauge change only, the state is unchanged), then
+ *   dev_out = H_eff(node) dev_in,
+ * both device buffers of one node tensor (complex, node tensor layout,
+ * shape of `node`), owned by the caller; they must not overlap.  The centre
+ * stays at `node`; the next ttns_tdvp_step moves it back to the root.
+ * Asynchronous on the context's stream.  TTNS_EINVAL for a bad tree / node
+ * index or NULL buffers. */
 int ttns_apply_heff(ttns_ctx *ctx, int32_t tree, int32_t node,
                     const void *dev_in, void *dev_out);
 
-/* n_steps second-order TDVP steps of size dt (Hamiltonian time units) on
- * every tree: pre-order sweep with h = dt/2 then the adjoint post-order
- * sweep; observables recorded after every step.  Asynchronous. */
+/* n_steps second-order time steps of size dt (inverse units of the
+ * Hamiltonian's energies) of the time-dependent variational principle
+ * (Methods, "Tensor Network States"; section "TTNS for vibronic quantum
+ * dynamics": each tensor is evolved in turn with its H_eff) on every tree:
+ * the pre-order sweep with h = dt/2 (node forward exp(-i h H_eff), then for
+ * each child: QR towards it, environment update, bond matrix backward
+ * exp(+i h H_bond), absorb) followed by the adjoint post-order sweep; the
+ * local exponentials are Lanczos with krylov_dim vectors.  Observables are
+ * recorded after every step.  Asynchronous: a numerical failure inside the
+ * steps (TTNS_ENUMERIC) is reported by the next ttns_observe.
+ * TTNS_EINVAL for n_steps < 0 or a non-finite dt. */
 int ttns_tdvp_step(ttns_ctx *ctx, double dt, int32_t n_steps);
 
-/* Copy an observable to host memory (synchronises the stream).  n_out is the
- * capacity of host_out in doubles; TTNS_EINVAL if too small. */
+/* Copy an observable of `tree` to host memory (synchronises the stream):
+ * the electronic populations and reduced density matrix of the root
+ * (section "Fission dynamics in DP-Mes": populations of the diabatic states),
+ * chain-head occupations, norm, energy, bond entanglement entropy (section
+ * "TTNS for vibronic quantum dynamics": S = -Tr rho ln rho), the record
+ * history, a node tensor, statistics.  `index` is the node for
+ * TTNS_OBS_TENSOR / TTNS_OBS_ENTROPY.  host_out (caller-owned) holds n_out
+ * doubles.  TTNS_EINVAL if n_out is too small or the kind / index is bad;
+ * TTNS_ENUMERIC if a step of this tree produced a non-finite record or a QR
+ * without completion vector (the values are then not returned, except for
+ * TTNS_OBS_STATS, _RECORD_SIZE, _BOND_DIMS and _STEP_FLOPS). */
 int ttns_observe(ttns_ctx *ctx, int32_t kind, int32_t tree, int32_t index,
                  double *host_out, size_t n_out);
 
@@ -259,8 +299,15 @@ int ttns_profile_kernel(ttns_ctx *ctx, int32_t kernel, double *total_ms,
  * full length + 1. */
 int ttns_tuning_report(const ttns_ctx* ctx, char* out, size_t n, size_t* needed);
 
+/* Release the context (host memory, captured graphs, its capture stream);
+ * the caller's workspace is not freed.  NULL is accepted. */
 int ttns_destroy(ttns_ctx *ctx);
-const char *ttns_last_error(void);
+
+/* Message of the last failed call on `ctx`, or, with ctx = NULL, of the last
+ * failed call of the calling thread (the only one for a build or size query
+ * that produced no context).  The string stays valid until the next call
+ * that fails on the same context / thread. */
+const char *ttns_last_error(const ttns_ctx *ctx);
 
 #ifdef __cplusplus
 }

@@ -41,8 +41,6 @@ constexpr int kMfmaMinSize = 16384;  // nodes this large use the matrix cores
 constexpr size_t kGraphSegment = 8192;  // launches per captured graph
 constexpr int kQrOneGroupRows = 4096;   // tallest QR left to one workgroup
 constexpr int kSplitLanes = 65536;      // scalar applies spread small nodes over up to this many lanes
-constexpr int kCoopMembers = 32;        // default workgroups of the cooperative executor
-constexpr int kCoopWideVbs = 8;         // ops over more than this many vbs per member run wide
 
 // Channel of an environment: the block Hamiltonian (kind 0), one end of a
 // two-node term (kind 1: term k, end 0 = node_a / 1 = node_b) or a recorded
@@ -219,17 +217,6 @@ struct ttns_ctx {
   std::vector<hipGraph_t> graphs;
   std::vector<hipGraphExec_t> gexecs;
   bool persistent = false;
-  bool coop = false;               // cooperative executor
-  int coop_members = 0;            // its workgroups (all on one XCD)
-  int coop_stride = 1;             // XCDs the dispatcher deals workgroups over
-  unsigned coop_xcc = 0;           // XCC id of workgroup 0
-  size_t o_bar = 0;                // its GridBar
-  GridBar* d_bar = nullptr;
-  struct Launch {
-    int begin, end;  // a cooperative stretch of the step program, or
-    int single;      // >= 0: one op launched on its own (matrix-core groups, wide ops)
-  };
-  std::vector<Launch> coop_plan;
   bool profile = false;
   double prof_ms = 0.0, prof_flops = 0.0;
   int64_t prof_n = 0;
@@ -250,6 +237,7 @@ struct ttns_ctx {
   std::map<std::string, int> tune_heff;  // node class -> 0 scalar, else the matrix-core tile (op.i1 code)
   std::map<std::string, int> tune_qr;    // QR shape -> 0 one workgroup, k > 0 wide with k workgroups
   std::string tune_report;
+  std::string err;  // message of the last failed call on this context
 };
 
 namespace {
@@ -563,10 +551,10 @@ struct Builder {
   static int nvb_of(int n) { return (n + kBlock - 1) / kBlock; }
   // log2 of the lanes per element of a scalar apply over n elements: up to
   // 8, as long as the grid stays within kSplitLanes lanes.  Only the wide
-  // executor gains: the one-workgroup and one-XCD executors already have
-  // more elements than lanes and would only repeat the dot reductions.
+  // executor gains: the one-workgroup executor already has more elements
+  // than lanes and would only repeat the dot reductions.
   int apply_lg(int n) const {
-    if (c.persistent || c.coop) return 0;
+    if (c.persistent) return 0;
     int lg = 0;
     while (lg < 3 && ((size_t)n << (lg + 1)) <= (size_t)kSplitLanes) ++lg;
     return lg;
@@ -739,26 +727,36 @@ struct Builder {
       m.band_hi = k == 0 ? m.hi[k] : std::max(m.band_hi, m.hi[k]);
       return true;
     };
+    // host copy of a term's local operator (null: identity)
+    auto host_op = [&](const cd* dev) -> const std::vector<cd>* {
+      for (size_t k = 0; k < t.opdev.size(); ++k)
+        if (t.opdev[k] == dev) return &t.ht.ops[k];
+      return nullptr;
+    };
+    // algorithmic flops: one complex D x D by D x n_rest product per term and
+    // output physical index s whose band holds a nonzero weight (what the
+    // kernel multiplies on the matrix cores)
     auto finish = [&](ModeDesc& m) {
       m.n_rest = sh.size / (sh.dims[m.axis] * sh.dims[sh.phys_axis]);
       const double D = sh.dims[m.axis];
       const int dp = sh.dims[sh.phys_axis];
-      int pairs = 0;  // (s, o) combinations with a nonzero weight
-      for (int s = 0; s < dp; ++s)
-        for (int o = m.band_lo; o <= m.band_hi; ++o) {
-          if (s + o < 0 || s + o >= dp) continue;
-          bool any = false;
-          for (int e = 0; e < m.n_e; ++e) {
-            if (!m.op[e]) any = any || o == 0;
-            else if (o >= m.lo[e] && o <= m.hi[e]) {
-              const cd g = t.ht.ops[0].empty() ? cd{0, 0} : cd{1, 0};
-              (void)g;
-              any = true;
-            }
+      int active = 0;
+      for (int e = 0; e < m.n_e; ++e) {
+        const std::vector<cd>* op = m.op[e] ? host_op(m.op[e]) : nullptr;
+        for (int s = 0; s < dp; ++s) {
+          if (!m.op[e]) {
+            ++active;
+            continue;
           }
-          pairs += any;
+          bool any = false;
+          for (int o = std::max(m.lo[e], -s); o <= std::min(m.hi[e], dp - 1 - s); ++o) {
+            const cd g = op ? (*op)[(size_t)s * dp + s + o] : cd{1, 0};
+            any = any || g.x != 0.0 || g.y != 0.0;
+          }
+          active += any;
         }
-      m.flops = 8.0 * D * D * m.n_rest * pairs;
+      }
+      m.flops = 8.0 * D * D * m.n_rest * active;
     };
     std::vector<ModeDesc> groups;
     std::vector<int> gkey_axis, gkey_src;
@@ -1357,13 +1355,10 @@ int prepare(ttns_ctx& c, std::vector<TreeState>&& trees, const ttns_opts* opts, 
   if (o.record_capacity < 1) return fail(TTNS_EINVAL, "record_capacity must be >= 1");
   if (!(o.rank_tol > 0) || !(o.breakdown_tol > 0)) return fail(TTNS_EINVAL, "tolerances must be > 0");
   if (o.precision < TTNS_FP64 || o.precision > TTNS_BF16X3) return fail(TTNS_EINVAL, "bad precision");
-  if (o.executor < TTNS_EXEC_AUTO || o.executor > TTNS_EXEC_COOPERATIVE) return fail(TTNS_EINVAL, "bad executor");
+  if (o.executor < TTNS_EXEC_AUTO || o.executor > TTNS_EXEC_PERSISTENT) return fail(TTNS_EINVAL, "bad executor");
   if (o.flags & ~(TTNS_FLAG_MFMA_ALL | TTNS_FLAG_AUTOTUNE)) return fail(TTNS_EINVAL, "unknown option flags");
-  if (o.coop_workgroups < 0 || o.coop_workgroups > kXccProbe)
-    return fail(TTNS_EINVAL, "coop_workgroups must be in [0, 1024]");
   c.opts = o;
   c.trees = std::move(trees);
-  c.coop = o.executor == TTNS_EXEC_COOPERATIVE;
   c.persistent = (o.executor == TTNS_EXEC_PERSISTENT) ||
                  (o.executor == TTNS_EXEC_AUTO && c.trees.size() > 1);
   for (auto& t : c.trees) {
@@ -1470,9 +1465,8 @@ int prepare(ttns_ctx& c, std::vector<TreeState>&& trees, const ttns_opts* opts, 
   c.o_modes = take(c.modes.size() * sizeof(ModeDesc));
   c.o_bonds = take(c.bonds.size() * sizeof(BondDesc));
   c.o_trees = take(c.trees.size() * sizeof(TreeDev));
-  // the op table is read by the persistent and cooperative executors
-  c.o_prog = take((c.persistent || c.coop) ? persistent_prog.size() * sizeof(Op) : 0);
-  c.o_bar = take(sizeof(GridBar));
+  // the op table is read by the persistent executor
+  c.o_prog = take(c.persistent ? persistent_prog.size() * sizeof(Op) : 0);
   c.o_begin = take(c.trees.size() * sizeof(int));
   c.o_end = take(c.trees.size() * sizeof(int));
   c.total = align256(off);
@@ -1495,7 +1489,6 @@ int prepare(ttns_ctx& c, std::vector<TreeState>&& trees, const ttns_opts* opts, 
   c.tables.bonds = (const BondDesc*)(c.ws + c.o_bonds);
   c.tables.trees = (const TreeDev*)(c.ws + c.o_trees);
   c.d_ops = (Op*)(c.ws + c.o_prog);
-  c.d_bar = (GridBar*)(c.ws + c.o_bar);
   c.d_begin = (int*)(c.ws + c.o_begin);
   c.d_end = (int*)(c.ws + c.o_end);
   // zero the workspace once (environments, scalars, counters, records)
@@ -1523,49 +1516,8 @@ int prepare(ttns_ctx& c, std::vector<TreeState>&& trees, const ttns_opts* opts, 
   if ((rc = upload(c, c.o_modes, c.modes.data(), c.modes.size() * sizeof(ModeDesc)))) return rc;
   if ((rc = upload(c, c.o_bonds, c.bonds.data(), c.bonds.size() * sizeof(BondDesc)))) return rc;
   if ((rc = upload(c, c.o_trees, tdev.data(), tdev.size() * sizeof(TreeDev)))) return rc;
-  if (c.persistent || c.coop)
+  if (c.persistent)
     if ((rc = upload(c, c.o_prog, persistent_prog.data(), persistent_prog.size() * sizeof(Op)))) return rc;
-  if (c.coop) {
-    // how the dispatcher deals the workgroups of a cooperative launch over
-    // the XCDs: workgroup b to XCD (b mod stride) is what the members' L2
-    // sharing relies on; any other dealing refuses the executor
-    const int maxb = coop_max_blocks();
-    const int pb = std::min(maxb, kXccProbe);
-    if (pb < 1) return fail(TTNS_EDEVICE, "cooperative launch not available on this device");
-    HIPCHK(probe_xcc_map(c.d_bar, pb, c.stream));
-    std::vector<unsigned> ids(pb);
-    HIPCHK(hipMemcpyAsync(ids.data(), c.d_bar->xcc, pb * sizeof(unsigned), hipMemcpyDeviceToHost, c.stream));
-    HIPCHK(hipStreamSynchronize(c.stream));
-    int stride = pb;
-    for (int b = 1; b < pb; ++b)
-      if (ids[b] == ids[0]) {
-        stride = b;
-        break;
-      }
-    bool dealt = true;
-    for (int b = 0; b < pb; ++b) dealt = dealt && ids[b] == ids[b % stride];
-    for (int x = 0; x < stride; ++x)
-      for (int y = x + 1; y < stride; ++y) dealt = dealt && ids[x] != ids[y];
-    if (!dealt) return fail(TTNS_EDEVICE, "cooperative executor: workgroups are not dealt round-robin over the XCDs");
-    c.coop_stride = stride;
-    c.coop_xcc = ids[0];
-    const int want = c.opts.coop_workgroups > 0 ? c.opts.coop_workgroups : kCoopMembers;
-    c.coop_members = std::max(1, std::min(want, maxb / stride));
-    // stretches between the ops launched on their own: matrix-core groups
-    // and ops too wide for one XCD
-    c.coop_plan.clear();
-    int start = 0;
-    const int wide_vbs = kCoopWideVbs * c.coop_members;
-    for (int i = 0; i <= (int)persistent_prog.size(); ++i) {
-      const bool single = i < (int)persistent_prog.size() &&
-                          (persistent_prog[i].type == OP_MODE || persistent_prog[i].nvb > wide_vbs);
-      if (i == (int)persistent_prog.size() || single) {
-        if (i > start) c.coop_plan.push_back({start, i, -1});
-        if (single) c.coop_plan.push_back({0, 0, i});
-        start = i + 1;
-      }
-    }
-  }
   if ((rc = upload(c, c.o_begin, c.tree_begin.data(), c.tree_begin.size() * sizeof(int)))) return rc;
   if ((rc = upload(c, c.o_end, c.tree_end.data(), c.tree_end.size() * sizeof(int)))) return rc;
   if ((rc = set_half(c, 0.0))) return rc;
@@ -1878,10 +1830,9 @@ void ttns_default_opts(ttns_opts* o) {
   o->record_capacity = 1;
   o->executor = TTNS_EXEC_AUTO;
   o->flags = 0;
-  o->coop_workgroups = 0;
 }
 
-const char* ttns_last_error(void) { return g_err.c_str(); }
+const char* ttns_last_error(const ttns_ctx* c) { return c ? c->err.c_str() : g_err.c_str(); }
 
 int ttns_ohmic_chain(double alpha, double wc, double s, int32_t L, double* c0, double* eps,
                      double* hop) {
@@ -2074,6 +2025,9 @@ static int build_common(std::vector<TreeState>&& ts, const ttns_opts* opts, void
     ts = std::move(copy);
   }
   rc = prepare(*c, std::move(ts), opts, ws, ws_bytes, stream, false, &dummy);
+  // the step graphs are captured here, so that the first ttns_tdvp_step
+  // costs what every later one does
+  if (!rc) rc = build_graph(*c);
   if (rc) {
     if (c->cap) (void)hipStreamDestroy(c->cap);
     return rc;
@@ -2102,7 +2056,7 @@ int ttns_star_build(const ttns_star_model* models, int32_t n_models, const ttns_
   return build_common(std::move(ts), opts, dev_ws, ws_bytes, hip_stream, out);
 }
 
-int ttns_apply_heff(ttns_ctx* c, int32_t tree, int32_t node, const void* dev_in, void* dev_out) {
+static int ttns_apply_heff_impl(ttns_ctx* c, int32_t tree, int32_t node, const void* dev_in, void* dev_out) {
   if (!c || tree < 0 || tree >= (int)c->trees.size()) return fail(TTNS_EINVAL, "ttns_apply_heff: bad tree");
   TreeState& t = c->trees[tree];
   if (node < 0 || node >= t.n || !dev_in || !dev_out) return fail(TTNS_EINVAL, "ttns_apply_heff: bad node");
@@ -2130,7 +2084,7 @@ int ttns_apply_heff(ttns_ctx* c, int32_t tree, int32_t node, const void* dev_in,
   return run_ops(*c, ops);
 }
 
-int ttns_tdvp_step(ttns_ctx* c, double dt, int32_t n_steps) {
+static int ttns_tdvp_step_impl(ttns_ctx* c, double dt, int32_t n_steps) {
   if (!c || n_steps < 0 || !std::isfinite(dt)) return fail(TTNS_EINVAL, "ttns_tdvp_step: bad arguments");
   if (n_steps == 0) return TTNS_OK;
   int rc = recentre(*c);
@@ -2142,33 +2096,26 @@ int ttns_tdvp_step(ttns_ctx* c, double dt, int32_t n_steps) {
       if ((rc = run_ops(*c, c->step_ops))) return rc;
     return TTNS_OK;
   }
-  if (c->coop) {
-    for (int s = 0; s < n_steps; ++s)
-      for (const auto& L : c->coop_plan) {
-        if (L.single >= 0) HIPCHK(launch_op(c->step_ops[L.single], c->tables, c->stream));
-        else
-          HIPCHK(launch_coop(c->d_ops, L.begin, L.end, c->tables, c->d_bar, c->coop_members, c->coop_stride,
-                             c->coop_xcc, c->stream));
-      }
-    return TTNS_OK;
-  }
   if ((rc = build_graph(*c))) return rc;
   for (int s = 0; s < n_steps; ++s)
     for (auto ge : c->gexecs) HIPCHK(hipGraphLaunch(ge, c->stream));
   return TTNS_OK;
 }
 
-int ttns_observe(ttns_ctx* c, int32_t kind, int32_t tree, int32_t index, double* host_out, size_t n_out) {
+static int ttns_observe_impl(ttns_ctx* c, int32_t kind, int32_t tree, int32_t index, double* host_out, size_t n_out) {
   if (!c || tree < 0 || tree >= (int)c->trees.size() || !host_out)
     return fail(TTNS_EINVAL, "ttns_observe: bad arguments");
-  if (c->coop) {  // a timed-out grid barrier invalidates every later result
-    int abort = 0;
-    HIPCHK(hipMemcpyAsync(&abort, &c->d_bar->abort, sizeof abort, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    if (abort) return fail(TTNS_EDEVICE, "cooperative executor: a grid barrier timed out");
-  }
   TreeState& t = c->trees[tree];
   HIPCHK(hipStreamSynchronize(c->stream));
+  if (kind != TTNS_OBS_STATS && kind != TTNS_OBS_RECORD_SIZE && kind != TTNS_OBS_BOND_DIMS &&
+      kind != TTNS_OBS_STEP_FLOPS) {
+    // numerical failures flagged by the kernels: bit 0 a QR that found no
+    // completion vector, bit 1 a non-finite record
+    int flags = 0;
+    HIPCHK(hipMemcpy(&flags, t.dev.stats + 3, sizeof(int), hipMemcpyDeviceToHost));
+    if (flags & 1) return fail(TTNS_ENUMERIC, "ttns_observe: a QR found no completion vector (non-finite state)");
+    if (flags & 2) return fail(TTNS_ENUMERIC, "ttns_observe: a step produced a non-finite norm or density matrix");
+  }
   int count = 0;
   HIPCHK(hipMemcpy(&count, t.dev.rec_count, sizeof(int), hipMemcpyDeviceToHost));
   const int rs = t.rec_size, nel = t.n_el;
@@ -2262,13 +2209,13 @@ int ttns_observe(ttns_ctx* c, int32_t kind, int32_t tree, int32_t index, double*
   }
 }
 
-int ttns_profile(ttns_ctx* c, int32_t enable) {
+static int ttns_profile_impl(ttns_ctx* c, int32_t enable) {
   if (!c) return fail(TTNS_EINVAL, "ttns_profile: null context");
   c->profile = enable != 0;
   return TTNS_OK;
 }
 
-int ttns_profile_read(ttns_ctx* c, int32_t reset, double* avg_ms, int64_t* launches, double* flops) {
+static int ttns_profile_read_impl(ttns_ctx* c, int32_t reset, double* avg_ms, int64_t* launches, double* flops) {
   if (!c) return fail(TTNS_EINVAL, "ttns_profile_read: null context");
   int rc = drain_profile(*c);
   if (rc) return rc;
@@ -2290,7 +2237,7 @@ int ttns_profile_read(ttns_ctx* c, int32_t reset, double* avg_ms, int64_t* launc
   return TTNS_OK;
 }
 
-int ttns_profile_kernel(ttns_ctx* c, int32_t kernel, double* total_ms, int64_t* launches, double* flops,
+static int ttns_profile_kernel_impl(ttns_ctx* c, int32_t kernel, double* total_ms, int64_t* launches, double* flops,
                         double* bytes) {
   if (!c || kernel < 0 || kernel >= TTNS_K_COUNT) return fail(TTNS_EINVAL, "ttns_profile_kernel: bad arguments");
   int rc = drain_profile(*c);
@@ -2311,6 +2258,31 @@ int ttns_tuning_report(const ttns_ctx* c, char* out, size_t n, size_t* needed) {
     out[k] = 0;
   }
   return TTNS_OK;
+}
+
+// Entry points on a context: the message of a failure is kept on the
+// context as well as for the calling thread.
+#define TTNS_CTX_CALL(c, expr)            \
+  do {                                    \
+    const int rc_ = (expr);               \
+    if (rc_ != TTNS_OK && (c)) (c)->err = g_err; \
+    return rc_;                           \
+  } while (0)
+
+int ttns_apply_heff(ttns_ctx* c, int32_t tree, int32_t node, const void* dev_in, void* dev_out) {
+  TTNS_CTX_CALL(c, ttns_apply_heff_impl(c, tree, node, dev_in, dev_out));
+}
+int ttns_tdvp_step(ttns_ctx* c, double dt, int32_t n_steps) { TTNS_CTX_CALL(c, ttns_tdvp_step_impl(c, dt, n_steps)); }
+int ttns_observe(ttns_ctx* c, int32_t kind, int32_t tree, int32_t index, double* host_out, size_t n_out) {
+  TTNS_CTX_CALL(c, ttns_observe_impl(c, kind, tree, index, host_out, n_out));
+}
+int ttns_profile(ttns_ctx* c, int32_t enable) { TTNS_CTX_CALL(c, ttns_profile_impl(c, enable)); }
+int ttns_profile_read(ttns_ctx* c, int32_t reset, double* avg_ms, int64_t* launches, double* flops) {
+  TTNS_CTX_CALL(c, ttns_profile_read_impl(c, reset, avg_ms, launches, flops));
+}
+int ttns_profile_kernel(ttns_ctx* c, int32_t kernel, double* total_ms, int64_t* launches, double* flops,
+                        double* bytes) {
+  TTNS_CTX_CALL(c, ttns_profile_kernel_impl(c, kernel, total_ms, launches, flops, bytes));
 }
 
 int ttns_destroy(ttns_ctx* c) {

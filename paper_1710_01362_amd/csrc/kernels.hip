@@ -30,7 +30,7 @@ struct Smem {
     cd lanes[kBlock];                 // wide-QR fold helpers
   };
   cd fold[64];
-  int ival[6];  // [4], [5]: the cooperative executor's barrier state
+  int ival[4];
   double dval[4];
 };
 
@@ -1610,190 +1610,6 @@ hipError_t launch_op(const Op& op, const DevTables& t, hipStream_t s) {
       return hipErrorInvalidValue;
   }
   return hipGetLastError();
-}
-
-// ------------------------------------------------------------ cooperative executor
-// The members of a cooperative launch all run on ONE XCD.  The launch has
-// `stride` x members workgroups; the dispatcher deals workgroup b to XCD
-// (b mod stride), which the host checks once at build (k_xcc_map), and only
-// the workgroups with b mod stride == 0 stay, each checking its XCC id
-// against the one found at build.  The members share that XCD's L2, so a
-// barrier needs no L2 write-back: every wave waits until its stores are
-// acknowledged (they are then in the shared L2), and after the wait each
-// member invalidates its CU's vector L1 (and the L2's non-coherent lines).
-// A kernel boundary, which writes the L2 back, separates a cooperative
-// stretch from the ops launched on their own (matrix-core groups and ops
-// too wide for one XCD).
-//
-// Within a stretch the virtual workgroups of each op are dealt out
-// round-robin over the members, a barrier separates consecutive ops, and
-// the fold of a reduction op runs in member 0 between two barriers (the
-// Lanczos ops instead fold their predecessor's partial sums in every member,
-// one barrier per op).
-// One-workgroup ops (QR, bond step, record) run in member 0 while the
-// others wait at the barrier.
-//
-// The barrier: each member adds to `count`; the last one resets it and
-// advances `gen`, which the others poll.  Waits are bounded: after
-// kSpinLimit polls a member raises `abort`, and every later barrier lets
-// all members through at once, so the launch always ends (the host then
-// reports the step as failed).
-constexpr long kSpinLimit = 1l << 22;
-
-__device__ __forceinline__ unsigned xcc_id() {
-  unsigned v;
-  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID, 0, 4)" : "=s"(v));
-  return v;
-}
-// this wave's global stores and atomics have been performed in the L2
-__device__ __forceinline__ void xcd_release() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
-// later loads of this CU miss its L1 and the L2's non-coherent lines
-__device__ __forceinline__ void xcd_acquire() {
-  asm volatile("buffer_inv sc1\n\ts_waitcnt vmcnt(0)" ::: "memory");
-}
-
-__device__ bool grid_sync(GridBar* bar, unsigned& gen, unsigned members, Smem& sm) {
-  xcd_release();  // every wave, before the workgroup barrier
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned target = gen + 1u;
-    const unsigned prev = atomicAdd(&bar->count, 1u);
-    if (prev == members - 1u) {
-      atomicExch(&bar->count, 0u);
-      xcd_release();  // the reset lands before the new generation
-      atomicExch(&bar->gen, target);
-    } else {
-      long spins = 0;
-      while (__hip_atomic_load(&bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != target) {
-        if (__hip_atomic_load(&bar->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-        if (++spins > kSpinLimit) {
-          atomicExch(&bar->abort, 1);
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
-    }
-    sm.ival[4] = __hip_atomic_load(&bar->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    xcd_acquire();
-  }
-  __syncthreads();
-  gen += 1u;
-  return sm.ival[4] == 0;
-}
-
-__global__ __launch_bounds__(kBlock) void k_coop(const Op* __restrict__ ops, int begin, int end, DevTables T,
-                                                 GridBar* bar, int stride, unsigned xcc) {
-  if (blockIdx.x % stride != 0) return;  // dealt to another XCD
-  __shared__ Smem sm;
-  __shared__ cd qr_lds[kQrLds];
-  const int b = blockIdx.x / stride, G = gridDim.x / stride;
-  if (threadIdx.x == 0) {
-    // a dealing other than the one found at build fails the step loudly
-    if (xcc_id() != xcc) atomicExch(&bar->abort, 1);
-    sm.ival[5] = (int)__hip_atomic_load(&bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  __syncthreads();
-  unsigned gen = (unsigned)sm.ival[5];
-  __syncthreads();
-  for (int i = begin; i < end; ++i) {
-    const Op op = ops[i];
-    const int nvb = op.nvb;
-    // the rest of a Lanczos process that already stopped: every member reads
-    // the same flag (set before the last barrier), so all skip together and
-    // the skipped ops cost no barrier
-    if ((op.type == OP_APPLY_LZ || op.type == OP_ORTH1 || op.type == OP_ORTH2) && T.trees[op.tree].scal->done)
-      continue;
-    switch (op.type) {
-      case OP_APPLY:
-        for (int vb = b; vb < nvb; vb += G) body_apply(op, T, vb);
-        break;
-      case OP_APPLY_LZ:  // the next op folds the partial dots in every member
-        for (int vb = b; vb < nvb; vb += G) body_apply_lz(op, T, vb, sm);
-        break;
-      case OP_NORM:
-        for (int vb = b; vb < nvb; vb += G) body_norm(op, T, vb, sm);
-        grid_sync(bar, gen, (unsigned)G, sm);
-        if (b == 0) fin_norm(op, T, nvb, sm);
-        break;
-      case OP_SCALE:
-        for (int vb = b; vb < nvb; vb += G) body_scale(op, T, vb);
-        break;
-      case OP_ORTH1:
-        orth1_prologue(op, T, sm, b == 0);
-        for (int vb = b; vb < nvb; vb += G) body_orth1(op, T, vb, sm);
-        break;
-      case OP_ORTH2:
-        orth2_prologue(op, sm);
-        for (int vb = b; vb < nvb; vb += G) body_orth2(op, T, vb, sm);
-        if (b == 0) fin_orth2(op, T, sm);
-        break;
-      case OP_COMBINE:
-        for (int vb = b; vb < nvb; vb += G) body_combine(op, T, vb, sm);
-        break;
-      case OP_QR:
-        if (b == 0) body_qr<false>(op, T, sm, qr_lds);
-        break;
-      case OP_CONTRACT:
-        for (int vb = b; vb < nvb; vb += G) body_contract(op, T, vb, sm, qr_lds);
-        grid_sync(bar, gen, (unsigned)G, sm);
-        if (b == 0) fin_contract(op, T, nvb);
-        break;
-      case OP_BOND:
-        if (b == 0) body_bond(op, T, sm, qr_lds);
-        break;
-      case OP_QRW: {
-        bool act = false;
-        for (int vb = b; vb < nvb; vb += G) act = body_qrw(op, T, vb, sm) || act;
-        // workgroup 0 holds virtual workgroup 0, whose answer is the op's
-        grid_sync(bar, gen, (unsigned)G, sm);
-        if (b == 0 && act) fin_qrw(op, T, nvb, sm);
-        break;
-      }
-      case OP_COPY:
-        for (int vb = b; vb < nvb; vb += G) body_copy(op, vb);
-        break;
-      case OP_DOT:
-        for (int vb = b; vb < nvb; vb += G) body_dot(op, T, vb, sm);
-        grid_sync(bar, gen, (unsigned)G, sm);
-        if (b == 0) fin_dot(op, T, nvb, sm);
-        break;
-      case OP_RECORD:
-        if (b == 0) body_record(op, T);
-        break;
-      case OP_SETH:
-        if (b == 0 && threadIdx.x == 0) *T.half_step = op.d0;
-        break;
-      default:
-        break;
-    }
-    grid_sync(bar, gen, (unsigned)G, sm);
-  }
-}
-
-int coop_max_blocks() {
-  int dev = 0, cus = 0, per = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_coop, kBlock, 0) != hipSuccess) return 0;
-  return cus * per;
-}
-
-hipError_t launch_coop(const Op* dev_ops, int begin, int end, const DevTables& t, GridBar* bar, int members,
-                       int stride, unsigned xcc, hipStream_t s) {
-  const int blocks = members * stride;
-  void* args[] = {(void*)&dev_ops, (void*)&begin, (void*)&end, (void*)&t, (void*)&bar, (void*)&stride,
-                  (void*)&xcc};
-  return hipLaunchCooperativeKernel((const void*)k_coop, dim3(blocks), dim3(kBlock), args, 0, s);
-}
-
-__global__ __launch_bounds__(64) void k_xcc_map(GridBar* bar) {
-  if (threadIdx.x == 0) bar->xcc[blockIdx.x] = xcc_id();
-}
-
-hipError_t probe_xcc_map(GridBar* bar, int blocks, hipStream_t s) {
-  if (blocks < 1 || blocks > kXccProbe) return hipErrorInvalidValue;
-  void* args[] = {(void*)&bar};
-  return hipLaunchCooperativeKernel((const void*)k_xcc_map, dim3(blocks), dim3(64), args, 0, s);
 }
 
 hipError_t launch_persistent(const Op* dev_ops, const int* dev_begin, const int* dev_end,

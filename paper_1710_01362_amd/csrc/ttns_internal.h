@@ -227,22 +227,6 @@ hipError_t launch_persistent(const Op* dev_ops, const int* dev_begin,
                              const DevTables& t, hipStream_t s);
 hipError_t launch_set_half_step(double* dst, double h, hipStream_t s);
 
-// Grid barrier state of the cooperative executor (in the workspace, zeroed),
-// and the XCC id of every workgroup of the build-time dealing probe.
-constexpr int kXccProbe = 1024;
-struct GridBar {
-  unsigned count, gen;
-  int abort, pad;
-  unsigned xcc[kXccProbe];
-};
-// resident workgroups of the cooperative kernel on the current device
-int coop_max_blocks();
-// members x stride workgroups; those with blockIdx mod stride == 0 (all on
-// XCC `xcc`) run ops [begin, end)
-hipError_t launch_coop(const Op* dev_ops, int begin, int end, const DevTables& t, GridBar* bar, int members,
-                       int stride, unsigned xcc, hipStream_t s);
-// bar->xcc[b] = XCC id of workgroup b of a cooperative launch of `blocks`
-hipError_t probe_xcc_map(GridBar* bar, int blocks, hipStream_t s);
 // MFMA limits: largest bond dimension per precision
 int mode_max_bond(int prec);
 // padded real operand size (2D rounded up to the MFMA K granule) of a group

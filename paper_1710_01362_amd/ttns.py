@@ -21,7 +21,7 @@ TTNS_EDEVICE = -3
 TTNS_ENUMERIC = -4
 
 TTNS_FP64, TTNS_FP32, TTNS_BF16X3 = 0, 1, 2
-TTNS_EXEC_AUTO, TTNS_EXEC_WIDE, TTNS_EXEC_PERSISTENT, TTNS_EXEC_COOPERATIVE = 0, 1, 2, 3
+TTNS_EXEC_AUTO, TTNS_EXEC_WIDE, TTNS_EXEC_PERSISTENT = 0, 1, 2
 TTNS_FLAG_MFMA_ALL = 1
 TTNS_FLAG_AUTOTUNE = 2
 
@@ -78,8 +78,7 @@ class StarModel(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("krylov_dim", C.c_int32),
                 ("breakdown_tol", C.c_double), ("rank_tol", C.c_double),
-                ("record_capacity", C.c_int32), ("executor", C.c_int32), ("flags", C.c_uint32),
-                ("coop_workgroups", C.c_int32)]
+                ("record_capacity", C.c_int32), ("executor", C.c_int32), ("flags", C.c_uint32)]
 
 
 _lib = None
@@ -115,7 +114,7 @@ def lib():
         L.ttns_profile_kernel.argtypes = [P, I, C.POINTER(D), C.POINTER(C.c_int64), C.POINTER(D), C.POINTER(D)]
         L.ttns_tuning_report.argtypes = [P, C.c_char_p, S, C.POINTER(S)]
         L.ttns_destroy.argtypes = [P]
-        L.ttns_last_error.argtypes = []
+        L.ttns_last_error.argtypes = [P]
         L.ttns_last_error.restype = C.c_char_p
         for name in EXPORTED:
             if name not in ("ttns_default_opts", "ttns_last_error"):
@@ -132,7 +131,7 @@ class TTNSError(RuntimeError):
 
 def check(rc):
     if rc != TTNS_OK:
-        raise TTNSError(rc, lib().ttns_last_error().decode())
+        raise TTNSError(rc, lib().ttns_last_error(None).decode())
 
 
 def default_opts(**kw):

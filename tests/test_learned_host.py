@@ -41,7 +41,7 @@ def test_bad_configs_rejected(bad):
     cfg = N.config(**kw)
     n = C.c_int64()
     assert N.lib().ttnn_param_count(C.byref(cfg), C.byref(n)) == T.TTNS_EINVAL
-    assert T.lib().ttns_last_error().decode().startswith("ttnn")
+    assert T.lib().ttns_last_error(None).decode().startswith("ttnn")
 
 
 def test_conditioning_output_too_small():
