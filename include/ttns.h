@@ -215,6 +215,23 @@ int ttns_star_build(const ttns_star_model *models, int32_t n_models,
                     const ttns_opts *opts, void *dev_ws, size_t ws_bytes,
                     void *hip_stream, ttns_ctx **out);
 
+/* ttns_star_build without a caller workspace, for callers that cannot
+ * allocate device memory (code that forbids hipMalloc, tight serving loops):
+ * the context lives in a static device array of 64 MiB per device
+ * (TTNS_ENOMEM if the trees need more; the size query tells), which every
+ * device that loads the library holds until the process ends.  One live
+ * context per device may use it: a second build on the same device fails
+ * with TTNS_EINVAL until the first is destroyed.  Contexts built here run
+ * their steps launch by launch on hip_stream (no graph is captured or
+ * instantiated), so ttns_tdvp_step on them allocates nothing either and may
+ * itself be captured by the caller.  The build, which uploads and
+ * synchronises, must not be captured.  Calls on two such contexts cannot
+ * overlap on one device (there is only one); TTNS_FLAG_AUTOTUNE is refused
+ * (its timing events allocate). */
+int ttns_star_build_noalloc(const ttns_star_model *models, int32_t n_models,
+                            const ttns_opts *opts, void *hip_stream,
+                            ttns_ctx **out);
+
 /* The local effective Hamiltonian of one node, H_eff(t) of the section "TTNS
  * for vibronic quantum dynamics" (every tensor is evolved with an H_eff built
  * from the full many-body state; the same operator whose eigenvalues give the

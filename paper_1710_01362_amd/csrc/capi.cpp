@@ -8,6 +8,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -238,6 +239,10 @@ struct ttns_ctx {
   std::map<std::string, int> tune_qr;    // QR shape -> 0 one workgroup, k > 0 wide with k workgroups
   std::string tune_report;
   std::string err;  // message of the last failed call on this context
+  // built by ttns_star_build_noalloc: the workspace is this device's static
+  // array, steps run launch by launch (no capture stream, no graphs)
+  bool noalloc = false;
+  int noalloc_dev = -1;
 };
 
 namespace {
@@ -1483,7 +1488,7 @@ int prepare(ttns_ctx& c, std::vector<TreeState>&& trees, const ttns_opts* opts, 
     return fail(TTNS_ENOMEM, "workspace too small: need " + std::to_string(c.total) + " bytes");
   c.ws_bytes = ws_bytes;
   c.stream = (hipStream_t)stream;
-  HIPCHK(hipStreamCreateWithFlags(&c.cap, hipStreamNonBlocking));
+  if (!c.noalloc) HIPCHK(hipStreamCreateWithFlags(&c.cap, hipStreamNonBlocking));
   c.tables.descs = (const ApplyDesc*)(c.ws + c.o_descs);
   c.tables.modes = (const ModeDesc*)(c.ws + c.o_modes);
   c.tables.bonds = (const BondDesc*)(c.ws + c.o_bonds);
@@ -1818,6 +1823,19 @@ double schmidt_entropy(const std::vector<cd>& R, int D) {
 }
 }  // namespace
 
+
+// ====================================================== allocation-free build
+// A workspace for callers that cannot allocate device memory: one static
+// array per device (each device that loads the library holds it until the
+// process ends), handed out to at most one live context at a time.
+namespace {
+constexpr size_t kNoallocBytes = (size_t)64 << 20;  // 64 MiB
+constexpr int kNoallocDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kNoallocDevices] = {};          // device address of `scratch` per device
+ttns_ctx* g_noalloc_owner[kNoallocDevices] = {};    // the context using it, if any
+}  // namespace
+
 // ====================================================================== C-ABI
 extern "C" {
 
@@ -2004,10 +2022,11 @@ static int autotune(ttns_ctx& c) {
 }
 
 static int build_common(std::vector<TreeState>&& ts, const ttns_opts* opts, void* ws, size_t ws_bytes,
-                        void* stream, ttns_ctx** out) {
+                        void* stream, ttns_ctx** out, bool noalloc = false) {
   if (!out) return fail(TTNS_EINVAL, "out is null");
   *out = nullptr;
   std::unique_ptr<ttns_ctx> c(new ttns_ctx());
+  c->noalloc = noalloc;
   size_t dummy = 0;
   int rc;
   if (opts && (opts->flags & TTNS_FLAG_AUTOTUNE)) {
@@ -2027,7 +2046,7 @@ static int build_common(std::vector<TreeState>&& ts, const ttns_opts* opts, void
   rc = prepare(*c, std::move(ts), opts, ws, ws_bytes, stream, false, &dummy);
   // the step graphs are captured here, so that the first ttns_tdvp_step
   // costs what every later one does
-  if (!rc) rc = build_graph(*c);
+  if (!rc && !noalloc) rc = build_graph(*c);
   if (rc) {
     if (c->cap) (void)hipStreamDestroy(c->cap);
     return rc;
@@ -2094,6 +2113,15 @@ static int ttns_tdvp_step_impl(ttns_ctx* c, double dt, int32_t n_steps) {
   if (c->profile && !c->persistent) {
     for (int s = 0; s < n_steps; ++s)
       if ((rc = run_ops(*c, c->step_ops))) return rc;
+    return TTNS_OK;
+  }
+  if (c->noalloc) {  // no graphs: their instantiation allocates
+    for (int s = 0; s < n_steps; ++s) {
+      if (c->persistent)
+        HIPCHK(launch_persistent(c->d_ops, c->d_begin, c->d_end, (int)c->trees.size(), c->tables, c->stream));
+      else if ((rc = run_ops(*c, c->step_ops)))
+        return rc;
+    }
     return TTNS_OK;
   }
   if ((rc = build_graph(*c))) return rc;
@@ -2287,6 +2315,11 @@ int ttns_profile_kernel(ttns_ctx* c, int32_t kernel, double* total_ms, int64_t* 
 
 int ttns_destroy(ttns_ctx* c) {
   if (!c) return TTNS_OK;
+  if (c->noalloc && c->noalloc_dev >= 0) {
+    (void)hipStreamSynchronize(c->stream);  // the next owner may clear the array
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (g_noalloc_owner[c->noalloc_dev] == c) g_noalloc_owner[c->noalloc_dev] = nullptr;
+  }
   drain_profile(*c);
   for (auto ge : c->gexecs) (void)hipGraphExecDestroy(ge);
   for (auto g : c->graphs) (void)hipGraphDestroy(g);
@@ -2296,3 +2329,44 @@ int ttns_destroy(ttns_ctx* c) {
 }
 
 }  // extern "C"
+
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+extern "C" int ttns_star_build_noalloc(const ttns_star_model* models, int32_t n_models, const ttns_opts* opts,
+                                       void* hip_stream, ttns_ctx** out) {
+  if (!out) return fail(TTNS_EINVAL, "ttns_star_build_noalloc: out is null");
+  *out = nullptr;
+  if (!models || n_models < 1) return fail(TTNS_EINVAL, "ttns_star_build_noalloc: no models");
+  if (opts && (opts->flags & TTNS_FLAG_AUTOTUNE))
+    return fail(TTNS_EINVAL, "ttns_star_build_noalloc: the autotuner's timing events allocate; build without it");
+  size_t need = 0;
+  int rc = ttns_star_workspace_size(models, n_models, opts, &need);
+  if (rc) return rc;
+  if (need > kNoallocBytes)
+    return fail(TTNS_ENOMEM, "ttns_star_build_noalloc: the trees need " + std::to_string(need) +
+                                 " bytes of workspace, the static workspace holds " + std::to_string(kNoallocBytes));
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoallocDevices) return fail(TTNS_EDEVICE, "ttns_star_build_noalloc: device index out of range");
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    // the array's address on this device (the host-side name is not one)
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(TTNS_EDEVICE, std::string("ttns_star_build_noalloc: hipGetSymbolAddress: ") + hipGetErrorString(e));
+    g_noalloc_ptr[dev] = p;
+  }
+  if (g_noalloc_owner[dev])
+    return fail(TTNS_EINVAL, "ttns_star_build_noalloc: the static workspace of device " + std::to_string(dev) +
+                                 " is held by another context; destroy it first");
+  std::string err;
+  auto ts = trees_from_star(models, n_models, err, rc);
+  if (rc) return fail(rc, err);
+  rc = build_common(std::move(ts), opts, g_noalloc_ptr[dev], kNoallocBytes, hip_stream, out, true);
+  if (rc) return rc;
+  (*out)->noalloc_dev = dev;
+  g_noalloc_owner[dev] = *out;
+  return TTNS_OK;
+}
+

@@ -34,7 +34,7 @@ EXPORTED = [
     "ttns_default_opts", "ttns_ohmic_chain", "ttns_workspace_size", "ttns_star_workspace_size",
     "ttns_build", "ttns_star_build", "ttns_apply_heff", "ttns_tdvp_step", "ttns_observe",
     "ttns_profile", "ttns_profile_read", "ttns_profile_kernel", "ttns_tuning_report", "ttns_destroy",
-    "ttns_last_error",
+    "ttns_last_error", "ttns_star_build_noalloc",
 ]
 # kernel ids (include/ttns.h) -> device symbol
 KERNELS = {0: "ttns::k_op<0> (scalar apply)", 1: "ttns::k_op<1> (scalar H_eff + Lanczos dots)",
@@ -106,6 +106,7 @@ def lib():
         L.ttns_star_workspace_size.argtypes = [C.POINTER(StarModel), I, C.POINTER(Opts), C.POINTER(S)]
         L.ttns_build.argtypes = [C.POINTER(Tree), I, C.POINTER(Opts), P, S, P, C.POINTER(P)]
         L.ttns_star_build.argtypes = [C.POINTER(StarModel), I, C.POINTER(Opts), P, S, P, C.POINTER(P)]
+        L.ttns_star_build_noalloc.argtypes = [C.POINTER(StarModel), I, C.POINTER(Opts), P, C.POINTER(P)]
         L.ttns_apply_heff.argtypes = [P, I, I, P, P]
         L.ttns_tdvp_step.argtypes = [P, D, I]
         L.ttns_observe.argtypes = [P, I, I, I, C.POINTER(D), S]
@@ -226,12 +227,24 @@ class Context:
     with ``trees=True``, a list of Tree structs from ``tree_struct``.
     """
 
-    def __init__(self, models, opts=None, device="cuda:0", trees=False, stream=None):
+    def __init__(self, models, opts=None, device="cuda:0", trees=False, stream=None, noalloc=False):
         import torch
         self.torch = torch
         L = lib()
         self.keep = []
         self.opts = opts if opts is not None else default_opts()
+        self.n_trees = len(models)
+        if noalloc:  # ttns_star_build_noalloc: the library's static workspace
+            arr = (StarModel * len(models))(*[star_model(m, self.keep) for m in models])
+            self.keep.append(arr)
+            self.device = torch.device(device)
+            self.ws = None
+            with torch.cuda.device(self.device):
+                self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+                self.ctx = C.c_void_p()
+                check(L.ttns_star_build_noalloc(arr, len(models), C.byref(self.opts),
+                                                C.c_void_p(self.stream.cuda_stream), C.byref(self.ctx)))
+            return
         if trees:
             arr = (Tree * len(models))(*models)
             size_fn, build_fn = L.ttns_workspace_size, L.ttns_build

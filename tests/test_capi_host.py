@@ -147,3 +147,19 @@ def test_overflowing_but_finite_hamiltonian_is_accepted_by_the_size_query():
     with a Hamiltonian of scale 1e300: finite, so validation accepts it."""
     rc, nbytes = _ws_size([W.spin_boson(L=3, d=3, D=2, delta=1e300, steps=2)], record_capacity=4)
     assert rc == T.TTNS_OK and nbytes > 0
+
+
+def test_noalloc_build_rejects_trees_beyond_the_static_workspace():
+    """The allocation-free build checks the size before any device call:
+    the five-level tree needs more than the 64 MiB static array."""
+    import ctypes as C
+    keep = []
+    arr = (T.StarModel * 1)(T.star_model(W.vibronic_reference(), keep))
+    ctx = C.c_void_p()
+    o = T.default_opts(record_capacity=2)
+    rc = T.lib().ttns_star_build_noalloc(arr, 1, C.byref(o), None, C.byref(ctx))
+    assert rc == T.TTNS_ENOMEM and not ctx.value
+    assert b"static workspace holds 67108864" in T.lib().ttns_last_error(None)
+    o = T.default_opts(record_capacity=2, flags=T.TTNS_FLAG_AUTOTUNE)
+    arr = (T.StarModel * 1)(T.star_model(W.spin_boson_reference(), keep))
+    assert T.lib().ttns_star_build_noalloc(arr, 1, C.byref(o), None, C.byref(ctx)) == T.TTNS_EINVAL
