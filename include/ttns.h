@@ -153,6 +153,16 @@ typedef struct {
   int32_t topology;          /* 0: chains hang off the root; 1: binary tree
                                 of ER nodes between the root and the chains */
   int32_t er_bond_dim;       /* D on root-ER and ER-ER edges                 */
+  const int32_t *obb_dim;    /* n_chains or NULL: optimised boson basis of
+                                each chain (Methods, "Tensor Network
+                                States": an expandable Fock basis behind a
+                                basis of obb_dim states).  With obb_dim[i]
+                                > 0 every site of chain i is a node without
+                                physical leg whose first child holds the
+                                local_dim Fock states behind a bond of
+                                dimension obb_dim[i] (the basis tensor) and
+                                whose second child is the next site; 0 keeps
+                                the plain chain                             */
 } ttns_star_model;
 
 typedef struct {
@@ -319,6 +329,12 @@ int ttns_tuning_report(const ttns_ctx* ctx, char* out, size_t n, size_t* needed)
 /* Release the context (host memory, captured graphs, its capture stream);
  * the caller's workspace is not freed.  NULL is accepted. */
 int ttns_destroy(ttns_ctx *ctx);
+
+/* sizeof of the structs of this ABI as the library was compiled: out[0..n)
+ * = ttns_c64, ttns_term, ttns_tree, ttns_star_model, ttns_opts, ttnn_config
+ * (0 past the end), so that a binding can refuse a library built from other
+ * headers.  TTNS_EINVAL for a NULL out or n < 1. */
+int ttns_struct_sizes(size_t *out, int32_t n);
 
 /* Message of the last failed call on `ctx`, or, with ctx = NULL, of the last
  * failed call of the calling thread (the only one for a build or size query

@@ -12,6 +12,11 @@ Tree layout (nodes numbered in pre-order, children in order):
 * node 0 is the electronic root (physical dimension = number of levels);
 * topology "star": chain i hangs directly below the root, site n's only
   child is site n+1;
+* with an optimised boson basis (chain key ``obb`` > 0, Methods "Tensor
+  Network States"), site n has no physical leg and two children: a basis
+  node holding the d Fock states of the site behind a bond of dimension
+  ``obb`` (the d -> obb basis tensor), then site n+1; the boson operators of
+  the site act on its basis node;
 * topology "er": the chain heads are joined to the root through a balanced
   binary tree of entanglement-renormalisation nodes (physical dimension 1),
   the construction Fig. 2 of the paper uses to avoid the order-(N+1) root.
@@ -70,6 +75,7 @@ def build_tree(model):
     def add_chain(i, p):
         ch = chains[i]
         d, D, L = ch["d"], ch["D"], ch["L"]
+        obb = int(ch.get("obb", 0))
         c0, eps, t = ohmic_chain(ch["alpha"], ch["wc"], ch.get("s", 1.0), L)
         b, bd, num = boson_ops(d)
         vac = np.zeros(d, dtype=np.complex128)
@@ -77,9 +83,17 @@ def build_tree(model):
         nodes = []
         prev = p
         for n in range(L):
-            node = tm.add_node(prev, d, D, vac, "site")
+            if obb:
+                # optimised boson basis: the site carries no physical leg; its
+                # first child holds the d Fock states behind a bond of
+                # dimension obb (the basis tensor), its second the next site
+                site = tm.add_node(prev, 1, D, [1.0], "site")
+                node = tm.add_node(site, d, obb, vac, "obb")
+                prev = site
+            else:
+                node = tm.add_node(prev, d, D, vac, "site")
+                prev = node
             nodes.append(node)
-            prev = node
         tm.heads[i] = nodes[0]
         tm.chain_nodes[i] = nodes
         A = np.asarray(ch["coupling"], dtype=np.complex128)

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "ttns_internal.h"
+#include "../../include/ttnn.h"
 
 namespace ttns {
 void ohmic_chain(double alpha, double wc, double s, int L, double* c0, double* eps, double* hop);
@@ -992,6 +993,9 @@ struct Builder {
       if (it != c.tune_qr.end()) choice = it->second;
     }
     if (lds || choice == 0 || (choice < 0 && rows <= kQrOneGroupRows)) {
+      // the 512-thread kernel with Q in LDS when it fits (the one-workgroup
+      // executor keeps the op's own workgroup)
+      o.i1 = (!c.persistent && qr_fast_fits(rows, cols)) ? 1 : 0;
       out.push_back(o);
       return;
     }
@@ -1077,6 +1081,10 @@ struct Builder {
       o.desc = ep.bond_desc;
       o.sign = +1;
       o.i0 = t.maxD * t.maxD;
+      // the 512-thread kernel with everything in LDS when it fits (the
+      // one-workgroup executor keeps the op's own workgroup)
+      const BondDesc& bd = c.bonds[ep.bond_desc];
+      o.i1 = (!c.persistent && bond_fast_fits(bd.Du, bd.Dv, c.opts.krylov_dim, bd.n_pairs)) ? 1 : 0;
       out.push_back(o);
     }
     apply_op(ep.absorb_desc);
@@ -1620,7 +1628,7 @@ int validate_program(ttns_ctx& c, const std::vector<Op>& ops, bool allow_user_xy
         const int cols = sh.dims[o.axis], rows = sh.size / cols;
         rc.in(o.p1, (size_t)sh.size * C, "QR tensor");
         if (o.nvb != 1 || cols > 64 || rows < cols || rows > d.max_rows || sh.size > d.ldv ||
-            o.axis == sh.phys_axis)
+            o.axis == sh.phys_axis || o.i1 < 0 || o.i1 > 1 || (o.i1 == 1 && !qr_fast_fits(rows, cols)))
           rc.err = "internal: QR shape";
         break;
       }
@@ -1669,7 +1677,9 @@ int validate_program(ttns_ctx& c, const std::vector<Op>& ops, bool allow_user_xy
           rc.in(b.Euk[k], (size_t)b.Du * b.Du * C, "bond Euk");
           rc.in(b.Evk[k], (size_t)b.Dv * b.Dv * C, "bond Evk");
         }
-        if (o.i0 < b.Du * b.Dv || b.Du > t.maxD || b.Dv > t.maxD) rc.err = "internal: bond size";
+        if (o.i0 < b.Du * b.Dv || b.Du > t.maxD || b.Dv > t.maxD || o.i1 < 0 || o.i1 > 1 ||
+            (o.i1 == 1 && !bond_fast_fits(b.Du, b.Dv, d.kmax, b.n_pairs)))
+          rc.err = "internal: bond size";
         break;
       }
       case OP_RECORD:
@@ -1851,6 +1861,14 @@ void ttns_default_opts(ttns_opts* o) {
 }
 
 const char* ttns_last_error(const ttns_ctx* c) { return c ? c->err.c_str() : g_err.c_str(); }
+
+int ttns_struct_sizes(size_t* out, int32_t n) {
+  if (!out || n < 1) return fail(TTNS_EINVAL, "ttns_struct_sizes: bad arguments");
+  const size_t s[] = {sizeof(ttns_c64), sizeof(ttns_term), sizeof(ttns_tree), sizeof(ttns_star_model),
+                      sizeof(ttns_opts), sizeof(ttnn_config)};
+  for (int32_t i = 0; i < n; ++i) out[i] = i < (int32_t)(sizeof(s) / sizeof(s[0])) ? s[i] : 0;
+  return TTNS_OK;
+}
 
 int ttns_ohmic_chain(double alpha, double wc, double s, int32_t L, double* c0, double* eps,
                      double* hop) {

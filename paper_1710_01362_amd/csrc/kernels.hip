@@ -807,6 +807,269 @@ __device__ void body_qr(const Op& op, const DevTables& T, Smem& sm, cd* lds) {
   else body_qr_t<false>(op, T, sm, nullptr, wrow, ctab);
 }
 
+// ------------------------------------------------------------ fast QR
+// The guarded QR of body_qr_t (classical Gram-Schmidt applied twice, column
+// by column, the same completion rule) organised for latency in one
+// workgroup of kQrThreads threads with Q in LDS.  Thread t owns rows
+// t, t + kQrThreads, ... (at most kQrRpt) and keeps their residual of the
+// current column in registers.  A projection Q^H v gives every coefficient
+// j a group of L lanes of one wavefront (L = 64, 32, 16 or 8, the widest
+// that leaves a group for every coefficient): the lanes sum interleaved
+// rows with four independent chains and a butterfly adds the lanes.  The
+// second pass also carries |v|^2, so that |v2|^2 = |v1|^2 - |h2|^2 (the
+// Pythagorean identity of the projection) needs no reduction of its own.
+// A completion vector u = e_row - Q Q^H e_row needs no reduction either:
+// |u|^2 = 1 - sum_j |Q_j[row]|^2 is the row's span weight, and
+// u^H v = v[row] up to rounding (v is orthogonal to the span).  Column k of
+// A is read from the node tensor one column ahead.
+
+// Workgroup barrier for data exchanged through LDS only: waits for this
+// wave's LDS operations but not for its global loads still in flight (so a
+// prefetch of the next column is not drained at every barrier, as the full
+// __syncthreads() fence would do).  The kernels using it exchange nothing
+// through global memory inside the workgroup.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// h[j] = sum_r conj(Q_j[r]) x[r] for j < k and, with `norm`, h[k] = |x|^2;
+// x = vb (LDS) or, with Q == nullptr, column j of the node tensor X (the
+// column norms at the start: every slot is a norm).  Ends with h visible.
+template <int L>
+__device__ void qf_slots(const cd* Q, const cd* vb, const cd* X, const int* roff, int cst, int rows, int k,
+                         int ns, cd* h) {
+  const int t = threadIdx.x;
+  const int j = t / L, g = t % L;
+  cd s0 = cz(), s1 = cz(), s2 = cz(), s3 = cz();
+  if (j < ns) {
+    if (!Q) {  // squared norm of tensor column j
+      int r = g;
+      for (; r + 3 * L < rows; r += 4 * L) {
+        s0.x += cabs2(X[roff[r] + j * cst]);
+        s1.x += cabs2(X[roff[r + L] + j * cst]);
+        s2.x += cabs2(X[roff[r + 2 * L] + j * cst]);
+        s3.x += cabs2(X[roff[r + 3 * L] + j * cst]);
+      }
+      for (; r < rows; r += L) s0.x += cabs2(X[roff[r] + j * cst]);
+    } else if (j < k) {
+      const cd* q = Q + (size_t)j * rows;
+      int r = g;
+      for (; r + 3 * L < rows; r += 4 * L) {
+        s0 = cjfma(q[r], vb[r], s0);
+        s1 = cjfma(q[r + L], vb[r + L], s1);
+        s2 = cjfma(q[r + 2 * L], vb[r + 2 * L], s2);
+        s3 = cjfma(q[r + 3 * L], vb[r + 3 * L], s3);
+      }
+      for (; r < rows; r += L) s0 = cjfma(q[r], vb[r], s0);
+    } else {  // j == k: |vb|^2
+      int r = g;
+      for (; r + 3 * L < rows; r += 4 * L) {
+        s0.x += cabs2(vb[r]);
+        s1.x += cabs2(vb[r + L]);
+        s2.x += cabs2(vb[r + 2 * L]);
+        s3.x += cabs2(vb[r + 3 * L]);
+      }
+      for (; r < rows; r += L) s0.x += cabs2(vb[r]);
+    }
+  }
+  cd s = cadd(cadd(s0, s1), cadd(s2, s3));
+#pragma unroll
+  for (int off = L >> 1; off > 0; off >>= 1) {
+    s.x += __shfl_xor(s.x, off);
+    s.y += __shfl_xor(s.y, off);
+  }
+  if (g == 0 && j < ns) h[j] = s;
+  lds_barrier();
+}
+__device__ void qf_project(const cd* Q, const cd* vb, const cd* X, const int* roff, int cst, int rows, int k,
+                           int ns, cd* h) {
+  if (ns <= kQrThreads / 64) qf_slots<64>(Q, vb, X, roff, cst, rows, k, ns, h);
+  else if (ns <= kQrThreads / 32) qf_slots<32>(Q, vb, X, roff, cst, rows, k, ns, h);
+  else if (ns <= kQrThreads / 16) qf_slots<16>(Q, vb, X, roff, cst, rows, k, ns, h);
+  else qf_slots<8>(Q, vb, X, roff, cst, rows, k, ns, h);
+}
+
+// w - sum_{j<k} Q_j[r] c[j] with four independent chains
+__device__ __forceinline__ cd qf_sub(const cd* Q, int rows, int r, int k, const cd* c, cd w) {
+  cd w1 = cz(), w2 = cz(), w3 = cz();
+  int j = 0;
+  for (; j + 3 < k; j += 4) {
+    const cd q0 = Q[(size_t)j * rows + r], q1 = Q[(size_t)(j + 1) * rows + r];
+    const cd q2 = Q[(size_t)(j + 2) * rows + r], q3 = Q[(size_t)(j + 3) * rows + r];
+    w = csub(w, make_double2(q0.x * c[j].x - q0.y * c[j].y, q0.x * c[j].y + q0.y * c[j].x));
+    w1 = csub(w1, make_double2(q1.x * c[j + 1].x - q1.y * c[j + 1].y, q1.x * c[j + 1].y + q1.y * c[j + 1].x));
+    w2 = csub(w2, make_double2(q2.x * c[j + 2].x - q2.y * c[j + 2].y, q2.x * c[j + 2].y + q2.y * c[j + 2].x));
+    w3 = csub(w3, make_double2(q3.x * c[j + 3].x - q3.y * c[j + 3].y, q3.x * c[j + 3].y + q3.y * c[j + 3].x));
+  }
+  for (; j < k; ++j) {
+    const cd q0 = Q[(size_t)j * rows + r];
+    w = csub(w, make_double2(q0.x * c[j].x - q0.y * c[j].y, q0.x * c[j].y + q0.y * c[j].x));
+  }
+  return cadd(cadd(w, w1), cadd(w2, w3));
+}
+
+__global__ __launch_bounds__(kQrThreads) void k_qr_fast(Op op, DevTables T) {
+  __shared__ __align__(16) unsigned char lds[kQrFastLds];
+  __shared__ int wfirst[kQrThreads / 64];
+  const TreeDev& tr = T.trees[op.tree];
+  const Shape& sh = T.descs[op.desc].sh;
+  const int ax = op.axis;
+  const int cols = sh.dims[ax], rows = sh.size / cols, cst = sh.stride[ax];
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  cd* Q = reinterpret_cast<cd*>(lds);   // column-major Q[c * rows + r]
+  cd* vb = Q + (size_t)rows * cols;    // residual of the current column
+  cd* h1 = vb + rows;                  // first-pass coefficients [0, 66)
+  cd* h2 = h1 + 66;                    // second pass [0, k) and |v1|^2 at [k]
+  cd* cn = h2 + 66;                    // column norms (real parts) [0, 64)
+  double* wrow = reinterpret_cast<double*>(cn + 64);  // sum_{j<k} |Q_j[r]|^2
+  int* roff = reinterpret_cast<int*>(wrow + rows);
+  unsigned short* ctab = reinterpret_cast<unsigned short*>(roff + rows);
+  cd* R = tr.R;
+  cd* X = op.p1;
+  for (int r = t; r < rows; r += kQrThreads) {
+    roff[r] = qr_row_offset(sh, ax, r);
+    wrow[r] = 0.0;
+    ctab[r] = (unsigned short)qr_candidate_row(sh, ax, r);
+  }
+  for (int i = t; i < cols * cols; i += kQrThreads) R[i] = cz();
+  __syncthreads();  // a full barrier: the zeroed R entries land before any thread writes one
+  qf_project(nullptr, nullptr, X, roff, cst, rows, 0, cols, cn);
+  double nrm = 0.0;
+  for (int c = 0; c < cols; ++c) nrm += cn[c].x;
+  const double tol = tr.rtol * sqrt(nrm);
+  cd a[kQrRpt], v[kQrRpt];
+#pragma unroll
+  for (int i = 0; i < kQrRpt; ++i) {
+    const int r = t + i * kQrThreads;
+    a[i] = r < rows ? X[roff[r]] : cz();
+  }
+  for (int k = 0; k < cols; ++k) {
+#pragma unroll
+    for (int i = 0; i < kQrRpt; ++i) v[i] = a[i];
+    if (k + 1 < cols) {  // the next column's loads stay in flight
+#pragma unroll
+      for (int i = 0; i < kQrRpt; ++i) {
+        const int r = t + i * kQrThreads;
+        a[i] = r < rows ? X[roff[r] + (k + 1) * cst] : cz();
+      }
+    }
+    const double c2 = cn[k].x;
+    double rn = 0.0;
+    if (c2 != 0.0 && k == 0) {
+      rn = sqrt(c2);
+    } else if (c2 != 0.0) {
+      // first pass
+#pragma unroll
+      for (int i = 0; i < kQrRpt; ++i) {
+        const int r = t + i * kQrThreads;
+        if (r < rows) vb[r] = v[i];
+      }
+      lds_barrier();
+      qf_project(Q, vb, nullptr, nullptr, 0, rows, k, k, h1);
+#pragma unroll
+      for (int i = 0; i < kQrRpt; ++i) {
+        const int r = t + i * kQrThreads;
+        if (r < rows) v[i] = qf_sub(Q, rows, r, k, h1, v[i]);
+      }
+      // a column no longer than tol is deficient whatever its projections:
+      // one pass gives its R entries and residual
+      if (sqrt(c2) > tol) {
+        lds_barrier();  // every thread has read vb
+#pragma unroll
+        for (int i = 0; i < kQrRpt; ++i) {
+          const int r = t + i * kQrThreads;
+          if (r < rows) vb[r] = v[i];
+        }
+        lds_barrier();
+        qf_project(Q, vb, nullptr, nullptr, 0, rows, k, k + 1, h2);
+        double hh = 0.0;
+        for (int j = 0; j < k; ++j) hh += cabs2(h2[j]);
+        rn = sqrt(fmax(h2[k].x - hh, 0.0));
+#pragma unroll
+        for (int i = 0; i < kQrRpt; ++i) {
+          const int r = t + i * kQrThreads;
+          if (r < rows) v[i] = qf_sub(Q, rows, r, k, h2, v[i]);
+        }
+        if (t < k) R[t * cols + k] = cadd(h1[t], h2[t]);
+      } else if (t < k) {
+        R[t * cols + k] = h1[t];
+      }
+    }
+    cd* qk = Q + (size_t)k * rows;
+    if (rn > tol) {
+      const double ir = 1.0 / rn;
+#pragma unroll
+      for (int i = 0; i < kQrRpt; ++i) {
+        const int r = t + i * kQrThreads;
+        if (r >= rows) continue;
+        const cd q = cscale(v[i], ir);
+        qk[r] = q;
+        wrow[r] += cabs2(q);
+      }
+      if (t == 0) R[k * cols + k] = make_double2(rn, 0.0);
+      continue;  // the next column's first barrier orders these writes
+    }
+    // completion: first candidate (completion order) whose squared distance
+    // from the span exceeds (rows - k) / (2 rows)
+    lds_barrier();  // wrow of every row is current; h1 / h2 are consumed
+    const double thr = 0.5 * (double)(rows - k) / (double)rows;
+    int chosen = -1;
+    for (int base = 0; base < rows && chosen < 0; base += kQrThreads) {
+      const int n = base + t;
+      const bool ok = n < rows && (1.0 - wrow[ctab[n]]) > thr;
+      const unsigned long long m = __ballot(ok);
+      if (lane == 0) wfirst[wid] = m ? base + wid * 64 + __ffsll((long long)m) - 1 : -1;
+      lds_barrier();
+      for (int w2 = 0; w2 < kQrThreads / 64 && chosen < 0; ++w2) chosen = wfirst[w2];
+      lds_barrier();
+    }
+    if (chosen < 0) {  // no candidate: a non-finite matrix (rows >= cols otherwise)
+      if (t == 0) atomicOr(&tr.stats[3], 1);
+      return;
+    }
+    const int row = ctab[chosen];
+    // coefficients conj(Q_j[row]) of the unit vector e_row
+    bool nz = false;
+    for (int j = t; j < k; j += kQrThreads) {
+      const cd q = Q[(size_t)j * rows + row];
+      h1[j] = make_double2(q.x, -q.y);
+      nz = nz || q.x != 0.0 || q.y != 0.0;
+    }
+    const double iu = 1.0 / sqrt(1.0 - wrow[row]);  // read before the row's weight changes
+    if (!__syncthreads_or(nz)) {
+      // e_row is exactly orthogonal to the span: q_k = e_row, R_kk = v[row]
+#pragma unroll
+      for (int i = 0; i < kQrRpt; ++i) {
+        const int r = t + i * kQrThreads;
+        if (r >= rows) continue;
+        qk[r] = make_double2(r == row ? 1.0 : 0.0, 0.0);
+        if (r == row) {
+          wrow[r] += 1.0;
+          R[k * cols + k] = v[i];
+        }
+      }
+    } else {
+      // q_k = (e_row - Q h) / |u|, R_kk = <q_k, v> = v[row] / |u|
+#pragma unroll
+      for (int i = 0; i < kQrRpt; ++i) {
+        const int r = t + i * kQrThreads;
+        if (r >= rows) continue;
+        const cd u = qf_sub(Q, rows, r, k, h1, make_double2(r == row ? 1.0 : 0.0, 0.0));
+        const cd q = cscale(u, iu);
+        qk[r] = q;
+        wrow[r] += cabs2(q);
+        if (r == row) R[k * cols + k] = cscale(v[i], iu);
+      }
+    }
+    if (t == 0) atomicAdd(&tr.stats[0], 1);
+    lds_barrier();  // h1 is rewritten by the next column
+  }
+  lds_barrier();
+  // scatter Q back into the node tensor (row owners)
+  for (int r = t; r < rows; r += kQrThreads) {
+    const int off = roff[r];
+    for (int c = 0; c < cols; ++c) X[off + c * cst] = Q[(size_t)c * rows + r];
+  }
+}
+
 // ------------------------------------------------------------ wide QR
 // The same column-by-column CGS2 with completion as body_qr, for matrices
 // too large for one workgroup's LDS, as a sequence of launches over row
@@ -1405,6 +1668,285 @@ __device__ void body_bond(const Op& op, const DevTables& T, Smem& sm, cd* lds) {
   else body_bond_t<false>(op, T, sm, nullptr);
 }
 
+// ------------------------------------------------------------ fast bond step
+// The bond step of body_bond_t (R <- exp(sign i h H_b) R by Lanczos with
+// classical Gram-Schmidt applied twice, breakdown, Krylov dimension kmax)
+// in one workgroup of kBondThreads threads with the Krylov basis, the work
+// vectors and the environment matrices in LDS.
+//   * H_b X = Eu X + X Ev^T + sum_k c_k Eu_k (X Ev_k^T): every thread owns
+//     a 2 x 2 output block and a 1/S share of the summation index (S = 8, 4,
+//     2 or 1, the most that keeps every block busy); the S partial blocks
+//     of adjacent lanes are added by butterflies.  First Y (both products)
+//     and every S_k = X Ev_k^T, then Y += sum_k c_k Eu_k S_k.
+//   * the dot products V^H w use groups of L lanes per vector (as the fast
+//     QR's projections), the second pass also carries |w|^2, and
+//     beta = sqrt(|w1|^2 - |h2|^2) (the Pythagorean identity of the
+//     projection); every thread keeps the residual of its elements in
+//     registers.
+constexpr int kBondThreads = 512;
+constexpr int kBondRpt = 8;  // elements per thread (Du Dv <= 4096)
+
+// one 2 x 2 block of sum_{m in [m0, m1)} A[a][m] B[m][c] (row-major, leading
+// dimensions lda / ldb) added to y[4] (rows a0, a1; columns c0, c1)
+__device__ __forceinline__ void bf_block(const cd* A, int lda, const cd* B, int ldb, int a0, int a1, int c0,
+                                         int c1, int m0, int m1, cd* y) {
+  for (int m = m0; m < m1; ++m) {
+    const cd p0 = A[a0 * lda + m], p1 = A[a1 * lda + m];
+    const cd q0 = B[m * ldb + c0], q1 = B[m * ldb + c1];
+    y[0] = cfma(p0, q0, y[0]);
+    y[1] = cfma(p0, q1, y[1]);
+    y[2] = cfma(p1, q0, y[2]);
+    y[3] = cfma(p1, q1, y[3]);
+  }
+}
+
+template <int S>
+__device__ __forceinline__ void bf_reduce(cd* y) {
+#pragma unroll
+  for (int off = S >> 1; off > 0; off >>= 1)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      y[q].x += __shfl_xor(y[q].x, off);
+      y[q].y += __shfl_xor(y[q].y, off);
+    }
+}
+
+// store (or with coef add coef *) a 2 x 2 block into Y (Du x Dv row-major)
+__device__ __forceinline__ void bf_store(cd* Y, int Du, int Dv, int a0, int c0, const cd* y, bool add, double coef) {
+  const int ia[4] = {a0, a0, a0 + 1, a0 + 1}, ic[4] = {c0, c0 + 1, c0, c0 + 1};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (ia[q] >= Du || ic[q] >= Dv) continue;
+    cd* o = Y + ia[q] * Dv + ic[q];
+    *o = add ? make_double2(fma(coef, y[q].x, o->x), fma(coef, y[q].y, o->y)) : y[q];
+  }
+}
+
+// W = H_b X (st: Eu, Ev^T, then Eu_k, Ev_k^T per pair; Sb: n_pairs scratch
+// matrices).  Ends with W visible to the workgroup.
+template <int S>
+__device__ void bf_apply(const BondDesc& b, const cd* st, const cd* X, cd* W, cd* Sb) {
+  const int Du = b.Du, Dv = b.Dv, np = b.n_pairs;
+  const int u2 = Du * Du, v2 = Dv * Dv;
+  const int bu = (Du + 1) >> 1, bv = (Dv + 1) >> 1, nb = bu * bv;
+  const int t = threadIdx.x;
+  // phase A: item (product p, block, chunk); p = 0: Y = Eu X + X Ev^T,
+  // p = 1 + k: S_k = X Ev_k^T
+  const int itemsA = (1 + np) * nb * S;
+  for (int base = 0; base < itemsA; base += kBondThreads) {  // uniform trip count
+    const int it = base + t;
+    const int ch = it % S, blk = (it / S) % nb, p = it / (S * nb);
+    const int a0 = 2 * (blk / bv), c0 = 2 * (blk % bv);
+    const int a1 = min(a0 + 1, Du - 1), c1 = min(c0 + 1, Dv - 1);
+    cd y[4] = {cz(), cz(), cz(), cz()};
+    if (it < itemsA) {
+      const int v0 = ch * Dv / S, v1 = (ch + 1) * Dv / S;
+      if (p == 0) {
+        const int m0 = ch * Du / S, m1 = (ch + 1) * Du / S;
+        bf_block(st, Du, X, Dv, a0, a1, c0, c1, m0, m1, y);           // Eu X
+        bf_block(X, Dv, st + u2, Dv, a0, a1, c0, c1, v0, v1, y);      // X Ev^T
+      } else {
+        const cd* EvT = st + (size_t)p * (u2 + v2) + u2;
+        bf_block(X, Dv, EvT, Dv, a0, a1, c0, c1, v0, v1, y);          // X Ev_k^T
+      }
+    }
+    bf_reduce<S>(y);
+    if (it < itemsA && ch == 0) bf_store(p == 0 ? W : Sb + (size_t)(p - 1) * Du * Dv, Du, Dv, a0, c0, y, false, 0.0);
+  }
+  lds_barrier();
+  if (np == 0) return;
+  // phase B: Y += sum_k c_k Eu_k S_k, item (block, chunk)
+  const int itemsB = nb * S;
+  for (int base = 0; base < itemsB; base += kBondThreads) {
+    const int it = base + t;
+    const int ch = it % S, blk = it / S;
+    const int a0 = 2 * (blk / bv), c0 = 2 * (blk % bv);
+    const int a1 = min(a0 + 1, Du - 1), c1 = min(c0 + 1, Dv - 1);
+    const int m0 = ch * Du / S, m1 = (ch + 1) * Du / S;
+    cd y[4] = {cz(), cz(), cz(), cz()};
+    for (int k = 0; k < np; ++k) {
+      cd z[4] = {cz(), cz(), cz(), cz()};
+      if (it < itemsB) bf_block(st + (size_t)(k + 1) * (u2 + v2), Du, Sb + (size_t)k * Du * Dv, Dv, a0, a1, c0, c1, m0, m1, z);
+      const double c = b.coef[k];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) y[q] = make_double2(fma(c, z[q].x, y[q].x), fma(c, z[q].y, y[q].y));
+    }
+    bf_reduce<S>(y);
+    if (it < itemsB && ch == 0) bf_store(W, Du, Dv, a0, c0, y, true, 1.0);
+  }
+  lds_barrier();
+}
+
+// h[i] = V_i^H x for i < cnt and, with `norm`, h[cnt] = |x|^2 (L lanes per
+// entry, four chains each); ends with h visible.
+template <int L>
+__device__ void bf_dots(const cd* V, int n, const cd* x, int cnt, bool norm, cd* h) {
+  const int t = threadIdx.x, i = t / L, g = t % L;
+  const int ns = cnt + (norm ? 1 : 0);
+  cd s0 = cz(), s1 = cz(), s2 = cz(), s3 = cz();
+  if (i < cnt) {
+    const cd* v = V + (size_t)i * n;
+    int p = g;
+    for (; p + 3 * L < n; p += 4 * L) {
+      s0 = cjfma(v[p], x[p], s0);
+      s1 = cjfma(v[p + L], x[p + L], s1);
+      s2 = cjfma(v[p + 2 * L], x[p + 2 * L], s2);
+      s3 = cjfma(v[p + 3 * L], x[p + 3 * L], s3);
+    }
+    for (; p < n; p += L) s0 = cjfma(v[p], x[p], s0);
+  } else if (i == cnt && norm) {
+    int p = g;
+    for (; p + 3 * L < n; p += 4 * L) {
+      s0.x += cabs2(x[p]);
+      s1.x += cabs2(x[p + L]);
+      s2.x += cabs2(x[p + 2 * L]);
+      s3.x += cabs2(x[p + 3 * L]);
+    }
+    for (; p < n; p += L) s0.x += cabs2(x[p]);
+  }
+  cd s = cadd(cadd(s0, s1), cadd(s2, s3));
+#pragma unroll
+  for (int off = L >> 1; off > 0; off >>= 1) {
+    s.x += __shfl_xor(s.x, off);
+    s.y += __shfl_xor(s.y, off);
+  }
+  if (g == 0 && i < ns) h[i] = s;
+  lds_barrier();
+}
+__device__ void bf_dots_any(const cd* V, int n, const cd* x, int cnt, bool norm, cd* h) {
+  const int ns = cnt + (norm ? 1 : 0);
+  if (ns <= kBondThreads / 64) bf_dots<64>(V, n, x, cnt, norm, h);
+  else if (ns <= kBondThreads / 32) bf_dots<32>(V, n, x, cnt, norm, h);
+  else bf_dots<16>(V, n, x, cnt, norm, h);  // ns <= kMaxKrylov + 1 < 32
+}
+
+// w - sum_{i<cnt} V_i[p] c[i], four chains
+__device__ __forceinline__ cd bf_sub(const cd* V, int n, int p, int cnt, const cd* c, cd w) {
+  cd w1 = cz(), w2 = cz(), w3 = cz();
+  int i = 0;
+  for (; i + 3 < cnt; i += 4) {
+    const cd v0 = V[(size_t)i * n + p], v1 = V[(size_t)(i + 1) * n + p];
+    const cd v2 = V[(size_t)(i + 2) * n + p], v3 = V[(size_t)(i + 3) * n + p];
+    w = csub(w, make_double2(v0.x * c[i].x - v0.y * c[i].y, v0.x * c[i].y + v0.y * c[i].x));
+    w1 = csub(w1, make_double2(v1.x * c[i + 1].x - v1.y * c[i + 1].y, v1.x * c[i + 1].y + v1.y * c[i + 1].x));
+    w2 = csub(w2, make_double2(v2.x * c[i + 2].x - v2.y * c[i + 2].y, v2.x * c[i + 2].y + v2.y * c[i + 2].x));
+    w3 = csub(w3, make_double2(v3.x * c[i + 3].x - v3.y * c[i + 3].y, v3.x * c[i + 3].y + v3.y * c[i + 3].x));
+  }
+  for (; i < cnt; ++i) {
+    const cd v0 = V[(size_t)i * n + p];
+    w = csub(w, make_double2(v0.x * c[i].x - v0.y * c[i].y, v0.x * c[i].y + v0.y * c[i].x));
+  }
+  return cadd(cadd(w, w1), cadd(w2, w3));
+}
+
+__global__ __launch_bounds__(kBondThreads) void k_bond_fast(Op op, DevTables T) {
+  __shared__ __align__(16) cd lds[kBondFastLds];
+  __shared__ Smem sm;  // Krylov exponential work (threads below kBlock)
+  __shared__ double al[kMaxKrylov], be[kMaxKrylov], wsum[kBondThreads / 64];
+  __shared__ cd h1[kMaxKrylov + 2], h2[kMaxKrylov + 2];
+  const TreeDev& tr = T.trees[op.tree];
+  const BondDesc& b = T.bonds[op.desc];
+  const int Du = b.Du, Dv = b.Dv, n = Du * Dv, np = b.n_pairs;
+  const int kmax = min(tr.kmax, n);
+  const int t = threadIdx.x;
+  cd* V = lds;                           // (kmax + 1) x n
+  cd* W = V + (size_t)(kmax + 1) * n;    // n
+  cd* Sb = W + n;                        // max(np, 1) x n
+  cd* st = Sb + (size_t)max(np, 1) * n;  // Eu, Ev^T, then Eu_k, Ev_k^T per pair
+  {
+    const int u2 = Du * Du, v2 = Dv * Dv;
+    cd* e = st;
+    for (int k = -1; k < np; ++k) {
+      const cd* su = k < 0 ? b.Eu : b.Euk[k];
+      const cd* sv = k < 0 ? b.Ev : b.Evk[k];
+      for (int i = t; i < u2; i += kBondThreads) e[i] = su[i];
+      for (int i = t; i < v2; i += kBondThreads) e[u2 + (i % Dv) * Dv + i / Dv] = sv[i];  // transposed
+      e += u2 + v2;
+    }
+  }
+  // |R| and V_0 = R / |R|; every thread keeps its elements in registers
+  cd w[kBondRpt];
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < kBondRpt; ++q) {
+    const int p = t + q * kBondThreads;
+    w[q] = p < n ? b.R[p] : cz();
+    s += cabs2(w[q]);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if ((t & 63) == 0) wsum[t >> 6] = s;
+  __syncthreads();  // also orders the staged matrices
+  s = 0.0;
+  for (int q = 0; q < kBondThreads / 64; ++q) s += wsum[q];
+  const double nx = sqrt(s);
+  if (nx == 0.0) return;  // uniform
+  const double inx = 1.0 / nx;
+#pragma unroll
+  for (int q = 0; q < kBondRpt; ++q) {
+    const int p = t + q * kBondThreads;
+    if (p < n) V[p] = cscale(w[q], inx);
+  }
+  lds_barrier();
+  const int bu = (Du + 1) >> 1, bv = (Dv + 1) >> 1, nb = bu * bv;
+  const int S = nb * 8 <= kBondThreads ? 8 : nb * 4 <= kBondThreads ? 4 : nb * 2 <= kBondThreads ? 2 : 1;
+  int k = 0;
+  for (int j = 0; j < kmax; ++j) {
+    const cd* vj = V + (size_t)j * n;
+    switch (S) {
+      case 8: bf_apply<8>(b, st, vj, W, Sb); break;
+      case 4: bf_apply<4>(b, st, vj, W, Sb); break;
+      case 2: bf_apply<2>(b, st, vj, W, Sb); break;
+      default: bf_apply<1>(b, st, vj, W, Sb); break;
+    }
+    // first pass
+    bf_dots_any(V, n, W, j + 1, false, h1);
+#pragma unroll
+    for (int q = 0; q < kBondRpt; ++q) {
+      const int p = t + q * kBondThreads;
+      if (p < n) w[q] = bf_sub(V, n, p, j + 1, h1, W[p]);
+    }
+    lds_barrier();  // W has been read
+#pragma unroll
+    for (int q = 0; q < kBondRpt; ++q) {
+      const int p = t + q * kBondThreads;
+      if (p < n) W[p] = w[q];
+    }
+    lds_barrier();
+    // second pass with |w1|^2
+    bf_dots_any(V, n, W, j + 1, true, h2);
+    double hh = 0.0;
+    for (int i = 0; i <= j; ++i) hh += cabs2(h2[i]);
+    const double ww = sqrt(fmax(h2[j + 1].x - hh, 0.0));
+    if (t == 0) al[j] = h1[j].x + h2[j].x;
+    k = j + 1;
+    if (j == kmax - 1) break;
+    if (ww <= tr.btol * nx) {
+      if (t == 0) atomicAdd(&tr.stats[1], 1);
+      break;
+    }
+    if (t == 0) be[j] = ww;
+    const double iw = 1.0 / ww;
+    cd* vn = V + (size_t)(j + 1) * n;
+#pragma unroll
+    for (int q = 0; q < kBondRpt; ++q) {
+      const int p = t + q * kBondThreads;
+      if (p < n) vn[p] = cscale(bf_sub(V, n, p, j + 1, h2, w[q]), iw);
+    }
+    lds_barrier();
+  }
+  __syncthreads();  // al / be complete (krylov_exp reads them)
+  krylov_exp(al, be, k, op.sign * (*T.half_step), sm);
+#pragma unroll
+  for (int q = 0; q < kBondRpt; ++q) {
+    const int p = t + q * kBondThreads;
+    if (p >= n) continue;
+    cd acc = cz();
+    for (int i = 0; i < k; ++i) acc = cfma(sm.vec[i], V[(size_t)i * n + p], acc);
+    b.R[p] = cscale(acc, nx);
+  }
+}
+
 // ------------------------------------------------------------ small ops
 __device__ void body_copy(const Op& op, int vb) {
   const int idx = vb * kBlock + threadIdx.x;
@@ -1585,6 +2127,14 @@ hipError_t launch_mode(const Op& op, const DevTables& t, hipStream_t s, int prec
 hipError_t launch_op(const Op& op, const DevTables& t, hipStream_t s) {
   const dim3 grid(op.nvb > 0 ? op.nvb : 1), block(kBlock);
   if (op.type == OP_MODE) return launch_mode(op, t, s, op.i0, op.n, op.axis);
+  if (op.type == OP_QR && op.i1 == 1) {
+    hipLaunchKernelGGL(k_qr_fast, dim3(1), dim3(kQrThreads), 0, s, op, t);
+    return hipGetLastError();
+  }
+  if (op.type == OP_BOND && op.i1 == 1) {
+    hipLaunchKernelGGL(k_bond_fast, dim3(1), dim3(kBondThreads), 0, s, op, t);
+    return hipGetLastError();
+  }
   switch (op.type) {
 #define TTNS_CASE(T_)                                            \
   case T_:                                                       \

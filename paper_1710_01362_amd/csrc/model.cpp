@@ -106,13 +106,25 @@ bool star_to_tree(const ttns_star_model& m, HostTree& t, std::string& err) {
     int op_A = add_op(t, A, n);
     std::vector<cd> vac(d, cd{0, 0});
     vac[0] = cd{1, 0};
+    const int obb = m.obb_dim ? m.obb_dim[i] : 0;
     int prev = p, head = -1;
-    std::vector<int> nodes;
+    std::vector<int> nodes;  // the nodes the boson operators act on
+    std::vector<cd> unit(1, cd{1, 0});
     for (int k = 0; k < L; ++k) {
-      int node = add_node(t, prev, d, D, vac);
+      int node;
+      if (obb > 0) {
+        // optimised boson basis: the site has no physical leg; its first
+        // child holds the d Fock states behind a bond of dimension obb, its
+        // second child is the next site
+        const int site = add_node(t, prev, 1, D, unit);
+        node = add_node(t, site, d, obb, vac);
+        prev = site;
+      } else {
+        node = add_node(t, prev, d, D, vac);
+        prev = node;
+      }
       nodes.push_back(node);
       if (k == 0) head = node;
-      prev = node;
     }
     t.terms.push_back(HostTerm{0, op_A, head, bo.x, c0});
     for (int k = 0; k < L; ++k) t.terms.push_back(HostTerm{nodes[k], bo.num, -1, -1, eps[k]});

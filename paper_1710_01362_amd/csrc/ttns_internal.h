@@ -23,6 +23,28 @@ constexpr int kRedStride = kMaxKrylov + 2;  // partial-sum slots per block
 constexpr int kMaxQrVb = 64;     // workgroups of a wide QR
 constexpr int kQrStride = 68;    // partial-sum slots per workgroup of a wide QR
 constexpr int kQrLdsEntries = 8800;  // complex entries of the single-workgroup QR's LDS
+constexpr int kQrThreads = 512;      // threads of the fast one-workgroup QR
+constexpr int kQrRpt = 2;            // rows per thread of the fast QR
+constexpr int kQrFastLds = 152 * 1024;  // LDS bytes of the fast QR
+// LDS bytes the fast QR of a rows x cols matrix needs: Q, the residual
+// vector, two coefficient vectors (+ norm slots), the column norms, and the
+// span weight, tensor offset and completion-order entry of every row
+constexpr size_t qr_fast_lds(int rows, int cols) {
+  return (size_t)rows * cols * 16 + (size_t)rows * 16 + 2 * 66 * 16 + 64 * 16 + (size_t)rows * 14 + 64;
+}
+// complex entries of the fast bond step's LDS: Krylov basis, work vector,
+// one scratch matrix per crossing term, the environment matrices
+constexpr int kBondFastLds = 9216;
+constexpr size_t bond_fast_lds(int Du, int Dv, int kmax, int pairs) {
+  return (size_t)(kmax + 2 + (pairs > 1 ? pairs : 1)) * Du * Dv + (size_t)(1 + pairs) * (Du * Du + Dv * Dv);
+}
+constexpr bool bond_fast_fits(int Du, int Dv, int kmax, int pairs) {
+  return Du * Dv <= 512 * 8 && bond_fast_lds(Du, Dv, kmax, pairs) <= (size_t)kBondFastLds;
+}
+constexpr bool qr_fast_fits(int rows, int cols) {
+  return cols >= 1 && cols <= 63 && rows >= cols && rows <= kQrThreads * kQrRpt && rows <= 65535 &&
+         qr_fast_lds(rows, cols) <= (size_t)kQrFastLds;
+}
 
 using cd = double2;  // complex double, interleaved (re, im)
 

@@ -34,7 +34,7 @@ EXPORTED = [
     "ttns_default_opts", "ttns_ohmic_chain", "ttns_workspace_size", "ttns_star_workspace_size",
     "ttns_build", "ttns_star_build", "ttns_apply_heff", "ttns_tdvp_step", "ttns_observe",
     "ttns_profile", "ttns_profile_read", "ttns_profile_kernel", "ttns_tuning_report", "ttns_destroy",
-    "ttns_last_error", "ttns_star_build_noalloc",
+    "ttns_last_error", "ttns_star_build_noalloc", "ttns_struct_sizes",
 ]
 # kernel ids (include/ttns.h) -> device symbol
 KERNELS = {0: "ttns::k_op<0> (scalar apply)", 1: "ttns::k_op<1> (scalar H_eff + Lanczos dots)",
@@ -72,7 +72,8 @@ class StarModel(C.Structure):
                 ("alpha", C.POINTER(C.c_double)), ("wc", C.POINTER(C.c_double)),
                 ("s", C.POINTER(C.c_double)), ("length", C.POINTER(C.c_int32)),
                 ("local_dim", C.POINTER(C.c_int32)), ("bond_dim", C.POINTER(C.c_int32)),
-                ("topology", C.c_int32), ("er_bond_dim", C.c_int32)]
+                ("topology", C.c_int32), ("er_bond_dim", C.c_int32),
+                ("obb_dim", C.POINTER(C.c_int32))]
 
 
 class Opts(C.Structure):
@@ -120,8 +121,22 @@ def lib():
         for name in EXPORTED:
             if name not in ("ttns_default_opts", "ttns_last_error"):
                 getattr(L, name).restype = C.c_int
+        L.ttns_struct_sizes.argtypes = [C.POINTER(S), I]
+        _check_struct_sizes(L)
         _lib = L
     return _lib
+
+
+def _check_struct_sizes(L):
+    """Refuse a library compiled from other headers than this binding's
+    struct layouts (a stale libttns.so would read the arguments wrongly)."""
+    from . import ttnn
+    mine = [C.sizeof(c64), C.sizeof(Term), C.sizeof(Tree), C.sizeof(StarModel), C.sizeof(Opts),
+            C.sizeof(ttnn.Config)]
+    theirs = (C.c_size_t * len(mine))()
+    if L.ttns_struct_sizes(theirs, len(mine)) != TTNS_OK or list(theirs) != mine:
+        raise RuntimeError("libttns.so was built from other headers than this binding (struct sizes %s vs %s): "
+                           "rebuild it" % (list(theirs), mine))
 
 
 class TTNSError(RuntimeError):
@@ -179,6 +194,7 @@ def star_model(m, keep):
         "L": _arr(C.c_int32, [c["L"] for c in ch]),
         "d": _arr(C.c_int32, [c["d"] for c in ch]),
         "D": _arr(C.c_int32, [c["D"] for c in ch]),
+        "obb": _arr(C.c_int32, [int(c.get("obb", 0)) for c in ch]),
     }
     keep.append(bufs)
     sm = StarModel()
@@ -191,6 +207,7 @@ def star_model(m, keep):
     sm.length, sm.local_dim, sm.bond_dim = bufs["L"], bufs["d"], bufs["D"]
     sm.topology = 1 if m["topology"] == "er" else 0
     sm.er_bond_dim = int(m.get("er_D", ch[0]["D"] if ch else 1))
+    sm.obb_dim = bufs["obb"]
     return sm
 
 

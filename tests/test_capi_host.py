@@ -163,3 +163,19 @@ def test_noalloc_build_rejects_trees_beyond_the_static_workspace():
     o = T.default_opts(record_capacity=2, flags=T.TTNS_FLAG_AUTOTUNE)
     arr = (T.StarModel * 1)(T.star_model(W.spin_boson_reference(), keep))
     assert T.lib().ttns_star_build_noalloc(arr, 1, C.byref(o), None, C.byref(ctx)) == T.TTNS_EINVAL
+
+
+def test_binding_refuses_a_library_with_other_struct_layouts():
+    """The binding compares its ctypes struct sizes with the library's at
+    load time; a stale library (built from other headers) is refused with a
+    message instead of reading the arguments wrongly."""
+    T.lib()  # the in-tree build matches
+
+    class Fake:
+        @staticmethod
+        def ttns_struct_sizes(out, n):
+            for i in range(n):
+                out[i] = 1
+            return T.TTNS_OK
+    with pytest.raises(RuntimeError, match="other headers"):
+        T._check_struct_sizes(Fake())

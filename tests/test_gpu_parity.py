@@ -122,6 +122,24 @@ def test_bond_entropy_matches_oracle(topology):
     ctx.close()
 
 
+@pytest.mark.parametrize("topology", ["star", "er"])
+def test_optimised_boson_basis_trees(topology):
+    """Chains with an optimised boson basis (sites without physical leg, the
+    Fock states on basis nodes behind a smaller bond): trajectories and
+    H_eff at site, basis and root nodes against the oracle."""
+    T = _T()
+    m = W.with_obb(dict(W.vibronic_small(steps=8, L=4, d=8, D=4), topology=topology), 3)
+    (hg,), _ = gpu_history([m], m["steps"])
+    _, ho = run(m)
+    assert_parity(hg, ho)
+    ctx = T.Context([m], opts=T.default_opts(record_capacity=4, executor=T.TTNS_EXEC_WIDE))
+    tt = TTNS(build_tree(m))
+    obb_nodes = [v for v in range(tt.n) if tt.tree.kind[v] == "obb"]
+    nodes = sorted(set([0, obb_nodes[0], obb_nodes[0] - 1, obb_nodes[-1], tt.n - 2]))
+    _apply_check(ctx, tt, nodes, np.random.default_rng(3), 1e-12, 1e-12, 1e-13)
+    ctx.close()
+
+
 def test_er_tree_eight_chains_small():
     m = W.vibronic(seed=4, n_chains=8, L=3, d=4, D=6, steps=4, topology="er", er_D=6)
     (hg,), _ = gpu_history([m], m["steps"])

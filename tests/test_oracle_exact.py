@@ -23,6 +23,11 @@ TREES = {
     "5 levels + 2x2 sites d3": lambda: W.vibronic(seed=6, n_levels=5, n_chains=2, L=2, d=3, D=100),
     "ER: 2 levels + 4x1 sites d2": lambda: dict(W.vibronic(seed=7, n_levels=2, n_chains=4, L=1, d=2, D=100),
                                                 topology="er", er_D=100),
+    # optimised boson basis: every site a node without physical leg plus a
+    # basis node holding its Fock states (full basis: exact manifold)
+    "OBB: spin + 3 sites d3": lambda: W.with_obb(W.spin_boson(L=3, d=3, D=100, delta=0.7, alpha=0.2, dt=0.1), 3),
+    "OBB: 3 levels + 2x2 sites d2": lambda: W.with_obb(W.vibronic(seed=8, n_levels=3, n_chains=2, L=2, d=2,
+                                                                  D=100), 2),
 }
 
 

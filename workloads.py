@@ -17,6 +17,7 @@ A model description is a dict with these keys:
                                 J(w) = 2 pi alpha wc (w/wc)^s theta(wc - w),
                                 chain length ``L``, local dimension ``d``,
                                 bond dimension ``D``
+               optional ``obb``: size of an optimised boson basis (0: none)
 ``topology``   "star" (chains hang off the electronic root) or "er" (a binary
                tree of entanglement-renormalisation nodes between the root and
                the chains, Fig. 2 of the paper)
@@ -158,6 +159,22 @@ def ensemble(seed=3, n=256, steps=100, dt=0.05):
     return out
 
 
+def with_obb(model, obb):
+    """The same model with an optimised boson basis of ``obb`` states on
+    every chain (chain key ``obb``; 0 removes it)."""
+    m = dict(model)
+    m["chains"] = [dict(c, obb=int(obb)) for c in model["chains"]]
+    return m
+
+
+def obb_tree(seed=5, L=30, d=40, obb=12, D=12, steps=100):
+    """Five-state vibronic tree whose four chains carry an optimised boson
+    basis: d Fock states per site behind ``obb`` basis states, chain bond
+    dimension D (the paper's run keeps 100 Fock states behind 40 basis
+    states and D = 30 along the chains)."""
+    return with_obb(vibronic(seed=seed, L=L, d=d, D=D, steps=steps), obb)
+
+
 def learned_sets(first_seed, count, **kw):
     """Parameter sets of the five-state family used as training / test data
     for the learned propagator (seeds first_seed .. first_seed+count-1)."""
@@ -169,8 +186,9 @@ def chain_count(model):
 
 
 def node_count(model):
-    """Number of tree nodes (root + ER nodes + chain sites)."""
-    n = 1 + sum(c["L"] for c in model["chains"])
+    """Number of tree nodes (root + ER nodes + chain sites, and one basis
+    node per site of a chain with an optimised boson basis)."""
+    n = 1 + sum(c["L"] * (2 if c.get("obb", 0) else 1) for c in model["chains"])
     if model["topology"] == "er":
         n += er_node_count(len(model["chains"]))
     return n
