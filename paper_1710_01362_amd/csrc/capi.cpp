@@ -692,16 +692,21 @@ struct Builder {
 
   bool plan_mode_groups(int v) {
     const int prec = c.opts.precision;
-    if (c.persistent) return false;  // the one-workgroup executor keeps the scalar apply
     const Shape& sh = t.shape[v];
-    const int maxD = mode_max_bond(prec);
+    // the one-workgroup executor runs the reduced-precision forms on the
+    // matrix cores with the small operand tile and 16-column blocks (bonds
+    // up to 32) and keeps the scalar FP64 apply otherwise
+    if (c.persistent && prec == TTNS_FP64) return false;
+    const int maxD = c.persistent ? 32 : mode_max_bond(prec);
     for (int a = 0; a < sh.rank; ++a)
       if (a != sh.phys_axis && sh.dims[a] > maxD) return false;
     std::vector<ApplyDesc> pre;
     ApplyDesc d = make_sum(v, -2, t.T[v], t.dev.W, pre);
     if (d.n_entries == 0) return false;
     t.mode_tile[v] = 0;
-    if (!c.tune_probe) {
+    if (c.persistent) {
+      t.mode_tile[v] = 1 | 4;  // small operands, 16 columns
+    } else if (!c.tune_probe) {
       auto it = c.tune_heff.find(heff_key(v, d, pre.size()));
       if (it != c.tune_heff.end()) {
         if (it->second == 0) return false;

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
+#include "mode_mfma_dev.h"
 #include "ttns_internal.h"
 
 namespace ttns {
@@ -2044,6 +2045,23 @@ __global__ __launch_bounds__(kBlock) void k_op(Op op, DevTables T) {
   }
 }
 
+// One matrix-core group run by the calling workgroup, all its blocks in
+// turn (the one-workgroup executor's form of the group kernel, with the
+// same block code and so the same arithmetic): the reduced-precision forms
+// only, with the small operand tile and 16 columns per block (the planner
+// admits bonds up to 32 there), which keeps the executor's registers free
+// of the larger tiles' accumulators.
+__device__ void mode_group_in_workgroup(const Op& op, const DevTables& Tb, unsigned char* lds) {
+  if (op.i0 == TTNS_FP32)
+    mfma::mode_all_blocks<TTNS_FP32, mfma::Prec<TTNS_FP32>::SMALL, 16>(op, Tb, op.n, op.axis, lds);
+  else if (op.i0 == TTNS_BF16X3)
+    mfma::mode_all_blocks<TTNS_BF16X3, mfma::Prec<TTNS_BF16X3>::SMALL, 16>(op, Tb, op.n, op.axis, lds);
+}
+static_assert(mfma::ModeSmem<TTNS_FP32, mfma::Prec<TTNS_FP32>::SMALL, 16>::kBytes + 16 * 4 + 16 <= sizeof(cd) * kQrLds &&
+                  mfma::ModeSmem<TTNS_BF16X3, mfma::Prec<TTNS_BF16X3>::SMALL, 16>::kBytes + 16 * 4 + 16 <=
+                      sizeof(cd) * kQrLds,
+              "matrix-core tiles exceed the executor's LDS");
+
 // One workgroup runs the operation list of one tree: ops[begin[b], end[b]).
 __global__ __launch_bounds__(kBlock) void k_persistent(const Op* __restrict__ ops,
                                                        const int* __restrict__ begin,
@@ -2114,6 +2132,9 @@ __global__ __launch_bounds__(kBlock) void k_persistent(const Op* __restrict__ op
         break;
       case OP_RECORD:
         body_record(op, T);
+        break;
+      case OP_MODE:
+        mode_group_in_workgroup(op, T, reinterpret_cast<unsigned char*>(qr_lds));
         break;
       default:
         break;

@@ -130,3 +130,39 @@ def test_large_er_tree_full_size():
     assert np.abs(h64["energy"] - h64["energy"][0]).max() <= 1e-10 * max(1.0, abs(h64["energy"][0]))
     pop = np.abs(np.einsum("kjj->kj", h16["rdm"]).real - np.einsum("kjj->kj", h64["rdm"]).real).max()
     assert pop <= 1e-5, pop
+
+
+@pytest.mark.parametrize("precision", [1, 2], ids=["fp32", "bf16x3"])
+def test_reduced_precision_in_the_persistent_batch(precision):
+    """The batched (one workgroup per tree) executor runs the reduced-precision
+    forms on the matrix cores too: an uneven batch of ensemble-recipe
+    instances in one persistent launch per step, each within 1e-5 in
+    populations of its FP64 oracle run, and visibly not the FP64 result
+    (the form is really used)."""
+    T = _T()
+    models = []
+    for m in W.ensemble(n=6):
+        m = dict(m)
+        m["chains"] = [dict(m["chains"][0], L=min(m["chains"][0]["L"], 12))]
+        m["steps"] = 12
+        models.append(m)
+    opts = dict(record_capacity=13, executor=T.TTNS_EXEC_PERSISTENT)
+    ctx = T.Context(models, opts=T.default_opts(precision=precision, **opts))
+    ctx.ttns_tdvp_step(models[0]["dt"], 12)
+    hs = [ctx.history(i) for i in range(len(models))]
+    ctx.close()
+    ctx = T.Context(models, opts=T.default_opts(**opts))
+    ctx.ttns_tdvp_step(models[0]["dt"], 12)
+    h64 = [ctx.history(i) for i in range(len(models))]
+    ctx.close()
+    worst, diff = 0.0, 0.0
+    for m, hg, hf in zip(models, hs, h64):
+        _, ho = run(m)
+        pg = np.einsum("kjj->kj", hg["rdm"]).real
+        po = np.einsum("kjj->kj", ho["rdm"]).real
+        worst = max(worst, np.abs(pg - po).max())
+        diff = max(diff, np.abs(hg["rdm"] - hf["rdm"]).max())
+        assert np.abs(hg["norm"] - 1).max() <= 1e-5
+    print("persistent batch, precision %d: population error vs oracle %.2e, vs FP64 GPU %.2e" % (precision, worst, diff))
+    assert worst <= 1e-5, worst
+    assert diff > 1e-13  # the contractions did run in reduced precision
