@@ -61,8 +61,22 @@ class TreeModel:
         return len(self.parent) - 1
 
 
-def build_tree(model):
-    """Translate a workload description into a TreeModel."""
+def momentum_op(d):
+    """p = i (b^+ - b) / sqrt(2) on |0..d-1> (Hermitian)."""
+    b, bd, _ = boson_ops(d)
+    return 1j * (bd - b) / np.sqrt(2.0)
+
+
+def build_tree(model, potential=False):
+    """Translate a workload description into a TreeModel.
+
+    With ``potential`` the operator sum is H - T instead of H, T the kinetic
+    energy of the environments' normal modes: for a chain with site energies
+    eps_n and hoppings t_n (the tridiagonal matrix M of its modes),
+    sum_modes (w/2) P^2 = (1/2) p^T M p with p_n = i (b_n^+ - b_n)/sqrt(2)
+    the chain-site momenta, i.e. the on-site terms (eps_n/2) p_n^2 and the
+    pair terms t_n p_n p_{n+1}.  Eq. (4)'s effective potential is built from
+    this operator."""
     tm = TreeModel()
     h_el = np.asarray(model["h_el"], dtype=np.complex128)
     n_el = h_el.shape[0]
@@ -103,6 +117,12 @@ def build_tree(model):
         for n in range(L - 1):
             tm.terms.append((t[n], nodes[n], bd, nodes[n + 1], b))
             tm.terms.append((t[n], nodes[n], b, nodes[n + 1], bd))
+        if potential:
+            p = momentum_op(d)
+            for n in range(L):
+                tm.terms.append((-0.5 * eps[n], nodes[n], p @ p, None, None))
+            for n in range(L - 1):
+                tm.terms.append((-t[n], nodes[n], p, nodes[n + 1], p))
 
     def group(p, idx):
         if len(idx) == 1:
