@@ -96,8 +96,10 @@ extern "C" {
                                 `index` (not the root) and its parent, i.e.
                                 of the bipartition (subtree of index | rest),
                                 1 double, from the current state (TTNS
-                                section: S = -Tr rho ln rho of a bond).  It
-                                moves the centre to the parent of `index`
+                                section: S = -Tr rho ln rho of a bond),
+                                computed on the device from the eigenvalues
+                                of R^H R, R the bond matrix of the gauge QR.
+                                It moves the centre to the parent of `index`
                                 (gauge only; the next ttns_tdvp_step returns
                                 it to the root)                              */
 
@@ -163,6 +165,13 @@ typedef struct {
                                 dimension obb_dim[i] (the basis tensor) and
                                 whose second child is the next site; 0 keeps
                                 the plain chain                             */
+  int32_t potential;         /* 0: the operator sum is H; 1: it is H - T, T
+                                the environments' kinetic energy (sum over
+                                each chain's normal modes of (w/2) P^2, i.e.
+                                (1/2) p^T M p over the site momenta p, M the
+                                chain's tridiagonal matrix): the operator of
+                                the effective potential of Eq. (4), whose
+                                context takes a state by ttns_copy_state    */
 } ttns_star_model;
 
 typedef struct {
@@ -283,6 +292,36 @@ int ttns_tdvp_step(ttns_ctx *ctx, double dt, int32_t n_steps);
  * TTNS_OBS_STATS, _RECORD_SIZE, _BOND_DIMS and _STEP_FLOPS). */
 int ttns_observe(ttns_ctx *ctx, int32_t kind, int32_t tree, int32_t index,
                  double *host_out, size_t n_out);
+
+/* Energy surfaces of the electronic system, Eqs. (3)-(4) (section "Fission
+ * dynamics in DP-Mes"): with the orthogonality centre moved to the root
+ * (a gauge change only), the bath states phi_i are the right singular
+ * vectors of the root tensor matricised as electronic level x all bonds
+ * (the system-environment Schmidt decomposition; retained while
+ * s_i > rank_tol s_0, at most n of them), and the matrix
+ *   M[(i n + j), (k n + l)] = <phi_i|<j| O |phi_k>|l>
+ * of the context's operator sum O (H: Eq. (3), the total energy surfaces;
+ * H - T for a model built with `potential`: Eq. (4), the potential energy
+ * surfaces) is formed on the device from applications of the root's
+ * effective operator.  host_values (cap doubles, cap >= n^2) receives the
+ * eigenvalues of M in ascending order (r n of them), *n_bath the number r of
+ * bath states, and host_matrix (optional, 2 (r n)^2 doubles: re, im,
+ * row-major) M itself.  Synchronises the stream.  TTNS_EINVAL for bad
+ * arguments or more than 8 electronic levels, TTNS_ENUMERIC for a zero
+ * state. */
+int ttns_energy_surfaces(ttns_ctx *ctx, int32_t tree, double rank_tol,
+                         int32_t *n_bath, double *host_values,
+                         double *host_matrix, size_t cap);
+
+/* Give tree dst_tree of dst the state of tree src_tree of src (the same
+ * topology and bond dimensions, possibly another operator sum, e.g. the
+ * H - T of Eq. (4)): src's centre is moved to the root, every node tensor is
+ * copied on the device, and dst rebuilds its environments towards the root
+ * for its own operator sum.  Both contexts on the current device; src's
+ * stream is synchronised first, dst's at the end.  dst's records are not
+ * updated.  TTNS_EINVAL when the trees or any node shape differ. */
+int ttns_copy_state(ttns_ctx *dst, int32_t dst_tree, ttns_ctx *src,
+                    int32_t src_tree);
 
 /* Kernels, for profiling.  Ids 0..15 are the one-operation kernels (their
  * device symbols are ttns::k_op<id>), 16..18 the matrix-core H_eff group

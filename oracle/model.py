@@ -76,7 +76,8 @@ def build_tree(model, potential=False):
     sum_modes (w/2) P^2 = (1/2) p^T M p with p_n = i (b_n^+ - b_n)/sqrt(2)
     the chain-site momenta, i.e. the on-site terms (eps_n/2) p_n^2 and the
     pair terms t_n p_n p_{n+1}.  Eq. (4)'s effective potential is built from
-    this operator."""
+    this operator (also selected by a true ``potential`` key of the model)."""
+    potential = potential or bool(model.get("potential", False))
     tm = TreeModel()
     h_el = np.asarray(model["h_el"], dtype=np.complex128)
     n_el = h_el.shape[0]

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libttns.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["kernels.hip", "mode_mfma.hip", "capi.cpp", "model.cpp", "learn.hip", "learn_capi.cpp"]
+SOURCES = ["kernels.hip", "mode_mfma.hip", "surfaces.hip", "capi.cpp", "model.cpp", "learn.hip", "learn_capi.cpp"]
 ARCH = os.environ.get("TTNS_OFFLOAD_ARCH", "gfx950")
 
 

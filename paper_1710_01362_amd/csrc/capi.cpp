@@ -43,6 +43,11 @@ constexpr int kMfmaMinSize = 16384;  // nodes this large use the matrix cores
 constexpr size_t kGraphSegment = 8192;  // launches per captured graph
 constexpr int kQrOneGroupRows = 4096;   // tallest QR left to one workgroup
 constexpr int kSplitLanes = 65536;      // scalar applies spread small nodes over up to this many lanes
+constexpr int kSurfVb = 256;            // workgroups of the energy-surface projections
+constexpr int kAuxMat = 64 * 64;        // entries of one eigensolver matrix
+// context-wide scratch: matrix, eigenvectors, eigenvalues (+ one result
+// double), projection partial sums
+size_t aux_bytes() { return 2 * kAuxMat * sizeof(cd) + 256 * sizeof(double) + (size_t)kSurfVb * 64 * sizeof(cd); }
 
 // Channel of an environment: the block Hamiltonian (kind 0), one end of a
 // two-node term (kind 1: term k, end 0 = node_a / 1 = node_b) or a recorded
@@ -204,6 +209,7 @@ struct ttns_ctx {
   std::vector<BondDesc> bonds;
   std::vector<ModeDesc> modes;
   size_t o_modes = 0;
+  size_t o_aux = 0;  // context-wide scratch of the energy surfaces and bond entropy
   size_t o_descs = 0, o_bonds = 0, o_trees = 0, o_half = 0, o_prog = 0, o_begin = 0, o_end = 0;
   size_t total = 0;
   DevTables tables{};
@@ -1322,6 +1328,9 @@ int upload(ttns_ctx& c, size_t off, const void* src, size_t bytes) {
 constexpr int kScratchDescs = 1 + kMaxTmp;  // ttns_apply_heff: H_eff + pre-stages
 
 int validate_program(ttns_ctx& c, const std::vector<Op>& ops, bool allow_user_xy);
+// programs whose inputs and outputs are workspace buffers other than the
+// planned ones (the energy-surface projections)
+int validate_program_aux(ttns_ctx& c, const std::vector<Op>& ops) { return validate_program(c, ops, true); }
 
 void set_tree_pointers(ttns_ctx& c, TreeState& t, char* base) {
   auto P = [&](size_t o_) { return (cd*)(base + o_); };
@@ -1399,6 +1408,10 @@ int prepare(ttns_ctx& c, std::vector<TreeState>&& trees, const ttns_opts* opts, 
   c.o_half = off;
   off += 256;
   c.tables.half_step = (double*)(base + c.o_half);
+  // energy surfaces / entropy scratch: two matrices of the eigensolver's
+  // largest size, its eigenvalues and the partial sums of the projections
+  c.o_aux = align256(off);
+  off = c.o_aux + aux_bytes();
   // plan: descriptors, init program and one step program per tree
   std::vector<Op> init_ops, persistent_prog;
   c.tree_begin.assign(c.trees.size(), 0);
@@ -1776,67 +1789,6 @@ namespace ttns {
 int set_error(int code, const std::string& msg) { return fail(code, msg); }
 }  // namespace ttns
 
-namespace {
-// -sum p ln p over p = sigma^2 / sum sigma^2, sigma the singular values of
-// the D x D complex R (row-major): eigenvalues of R^H R from cyclic Jacobi
-// rotations of its real symmetric 2D x 2D embedding [[X, -Y], [Y, X]]
-// (every eigenvalue twice).
-double schmidt_entropy(const std::vector<cd>& R, int D) {
-  const int N = 2 * D;
-  std::vector<double> A((size_t)N * N, 0.0);
-  for (int i = 0; i < D; ++i)
-    for (int j = 0; j < D; ++j) {
-      double x = 0.0, y = 0.0;  // (R^H R)_ij = sum_k conj(R_ki) R_kj
-      for (int k = 0; k < D; ++k) {
-        const cd a = R[(size_t)k * D + i], b = R[(size_t)k * D + j];
-        x += a.x * b.x + a.y * b.y;
-        y += a.x * b.y - a.y * b.x;
-      }
-      A[(size_t)i * N + j] = x;
-      A[(size_t)(D + i) * N + D + j] = x;
-      A[(size_t)(D + i) * N + j] = y;
-      A[(size_t)i * N + D + j] = -y;
-    }
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    double off = 0.0, tot = 0.0;
-    for (int p = 0; p < N; ++p)
-      for (int q = 0; q < N; ++q) {
-        tot += A[(size_t)p * N + q] * A[(size_t)p * N + q];
-        if (p != q) off += A[(size_t)p * N + q] * A[(size_t)p * N + q];
-      }
-    if (off <= 1e-30 * tot) break;
-    for (int p = 0; p < N; ++p)
-      for (int q = p + 1; q < N; ++q) {
-        const double apq = A[(size_t)p * N + q];
-        if (std::fabs(apq) < 1e-300) continue;
-        const double th = (A[(size_t)q * N + q] - A[(size_t)p * N + p]) / (2.0 * apq);
-        const double tn = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
-        const double cs = 1.0 / std::sqrt(1.0 + tn * tn), sn = tn * cs;
-        for (int k = 0; k < N; ++k) {
-          const double x = A[(size_t)k * N + p], y = A[(size_t)k * N + q];
-          A[(size_t)k * N + p] = cs * x - sn * y;
-          A[(size_t)k * N + q] = sn * x + cs * y;
-        }
-        for (int k = 0; k < N; ++k) {
-          const double x = A[(size_t)p * N + k], y = A[(size_t)q * N + k];
-          A[(size_t)p * N + k] = cs * x - sn * y;
-          A[(size_t)q * N + k] = sn * x + cs * y;
-        }
-      }
-  }
-  // each eigenvalue lambda appears twice: with q = lambda / (2 sum lambda)
-  // over the 2D diagonal, p = 2 q and -sum p ln p = -sum_2D q ln q - ln 2
-  double sum = 0.0;
-  for (int i = 0; i < N; ++i) sum += std::max(A[(size_t)i * N + i], 0.0);
-  if (!(sum > 0.0)) return 0.0;
-  double S = 0.0;
-  for (int i = 0; i < N; ++i) {
-    const double q = std::max(A[(size_t)i * N + i], 0.0) / sum;
-    if (q > 1e-300) S -= q * std::log(q);
-  }
-  return std::max(S - std::log(2.0), 0.0);
-}
-}  // namespace
 
 
 // ====================================================== allocation-free build
@@ -2248,11 +2200,15 @@ static int ttns_observe_impl(ttns_ctx* c, int32_t kind, int32_t tree, int32_t in
       b.move_to(index);
       b.move(index, par, false);
       if ((rc = validate_program(*c, ops, false)) || (rc = run_ops(*c, ops))) return rc;
+      // eigenvalues of R^H R (the squared Schmidt values) and -sum p ln p
       const int D = t.shape[index].dims[axis_of(t, index, par)];
-      std::vector<cd> R((size_t)D * D);
-      HIPCHK(hipMemcpyAsync(R.data(), t.dev.R, R.size() * sizeof(cd), hipMemcpyDeviceToHost, c->stream));
+      cd* G = (cd*)(c->ws + c->o_aux);
+      double* ev = (double*)(G + 2 * kAuxMat);
+      HIPCHK(launch_gram(t.dev.R, D, G, c->stream));
+      HIPCHK(launch_herm_eig(G, D, D, ev, nullptr, 1, c->stream));
+      HIPCHK(launch_entropy(ev, D, ev + 128, c->stream));
+      HIPCHK(hipMemcpyAsync(host_out, ev + 128, sizeof(double), hipMemcpyDeviceToHost, c->stream));
       HIPCHK(hipStreamSynchronize(c->stream));
-      host_out[0] = schmidt_entropy(R, D);
       return TTNS_OK;
     }
     default:
@@ -2311,6 +2267,119 @@ int ttns_tuning_report(const ttns_ctx* c, char* out, size_t n, size_t* needed) {
   return TTNS_OK;
 }
 
+// Energy surfaces (Eqs. 3-4): bath Schmidt states of the root, the matrix of
+// the context's operator sum between (bath state, electronic state)
+// products, its eigenvalues.
+static int ttns_energy_surfaces_impl(ttns_ctx* c, int32_t tree, double rank_tol, int32_t* n_bath,
+                                     double* host_values, double* host_matrix, size_t cap) {
+  if (!c || tree < 0 || tree >= (int)c->trees.size() || !host_values || !n_bath || !(rank_tol > 0) ||
+      !(rank_tol < 1))
+    return fail(TTNS_EINVAL, "ttns_energy_surfaces: bad arguments");
+  TreeState& t = c->trees[tree];
+  const int nel = t.n_el, size = t.shape[0].size, nb = size / nel;
+  if (nel > 8 || nel * nel > surf_eig_max())
+    return fail(TTNS_EINVAL, "ttns_energy_surfaces: at most 8 electronic levels");
+  if ((size_t)nel * nel > cap) return fail(TTNS_EINVAL, "ttns_energy_surfaces: host_values holds fewer than n^2 values");
+  if (2 * nel > t.kmax + 1) return fail(TTNS_EINVAL, "ttns_energy_surfaces: Krylov basis too small for the bath states");
+  int rc = recentre(*c);
+  if (rc) return rc;
+  cd* M = (cd*)(c->ws + c->o_aux);
+  cd* Wv = M + kAuxMat;
+  double* ev = (double*)(Wv + kAuxMat);
+  cd* part = (cd*)(ev + 256);
+  // rho^T = conj(rho) of the root (the contraction over all bonds)
+  {
+    std::vector<Op> ops;
+    Builder b{*c, t, tree, ops};
+    Op o = b.base(OP_CONTRACT, std::min(kMaxContractVb, std::max(1, (nb + 31) / 32)));
+    o.desc = t.heff_desc[0];
+    o.axis = 0;
+    o.p0 = t.T[0];
+    o.p2 = t.T[0];
+    o.p1 = M;
+    o.i0 = 0;
+    ops.push_back(o);
+    if ((rc = validate_program_aux(*c, ops))) return rc;
+    if ((rc = run_ops(*c, ops))) return rc;
+  }
+  // Schmidt decomposition C = U S Vh in two passes: the eigenvectors of rho
+  // rotate the rows of C to nearly orthogonal ones (U^H C), whose own Gram
+  // matrix is then graded (diagonal s_i^2), so a second eigen-decomposition
+  // gets the small singular values' directions to rounding relative to
+  // their size (rho alone would leave them at rounding relative to s_0)
+  const int nvb = std::min(kSurfVb, std::max(1, (nb + 1023) / 1024));
+  cd* Bm = t.dev.V;                            // rows U^H C: Krylov rows [0, n)
+  cd* B = t.dev.V + (size_t)nel * t.dev.ldv;   // bath states: rows [n, 2n)
+  HIPCHK(launch_herm_eig(M, nel, nel, ev, Wv, 1, c->stream));
+  HIPCHK(launch_bath_vectors(t.T[0], nb, nel, nb, Wv, ev, nel, 0, Bm, t.dev.ldv, c->stream));
+  HIPCHK(launch_surf_dots(Bm, t.dev.ldv, Bm, t.dev.ldv, nel, nb, nel, part, nvb, c->stream));
+  HIPCHK(launch_surf_fold(part, nvb, nel * nel, M, 1, 0, c->stream));
+  HIPCHK(launch_herm_eig(M, nel, nel, ev, Wv, 1, c->stream));
+  std::vector<double> lam(nel);
+  HIPCHK(hipMemcpyAsync(lam.data(), ev, nel * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  // retained bath states: s_i > rank_tol s_0, i.e. lambda_i > rank_tol^2 lambda_0
+  int r = 0;
+  for (int i = nel - 1; i >= 0; --i)
+    if (lam[i] > rank_tol * rank_tol * lam[nel - 1] && lam[i] > 0.0) ++r;
+  if (r == 0) return fail(TTNS_ENUMERIC, "ttns_energy_surfaces: the state is zero");
+  *n_bath = r;
+  const int N = r * nel;
+  HIPCHK(launch_bath_vectors(Bm, t.dev.ldv, nel, nb, Wv, ev, r, 1, B, t.dev.ldv, c->stream));
+  for (int k = 0; k < r; ++k)
+    for (int l = 0; l < nel; ++l) {
+      HIPCHK(launch_surf_fill(t.dev.X, B, t.dev.ldv, k, l, nel, nb, c->stream));
+      std::vector<Op> ops;
+      Builder b{*c, t, tree, ops};
+      if (!t.mode_groups[0].empty()) {
+        b.mode_apply(0, t.dev.X, t.dev.W);
+      } else {
+        for (int pid : t.heff_pre[0]) b.apply_op(pid, t.dev.X);
+        b.apply_op(t.heff_desc[0], t.dev.X);  // y = W
+      }
+      if ((rc = validate_program_aux(*c, ops))) return rc;
+      if ((rc = run_ops(*c, ops))) return rc;
+      HIPCHK(launch_surf_dots(B, t.dev.ldv, t.dev.W, nb, nel, nb, r, part, nvb, c->stream));
+      HIPCHK(launch_surf_fold(part, nvb, N, M, N, k * nel + l, c->stream));
+    }
+  HIPCHK(launch_herm_eig(M, N, N, ev, nullptr, 0, c->stream));
+  HIPCHK(hipMemcpyAsync(host_values, ev, N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  if (host_matrix)
+    HIPCHK(hipMemcpyAsync(host_matrix, M, (size_t)N * N * sizeof(cd), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return TTNS_OK;
+}
+
+// dst's tree takes src's state (same shapes), centre at the root, and
+// rebuilds its environments towards the root for its own operator sum.
+static int ttns_copy_state_impl(ttns_ctx* dst, int32_t dtree, ttns_ctx* src, int32_t stree) {
+  if (!dst || !src || dtree < 0 || dtree >= (int)dst->trees.size() || stree < 0 ||
+      stree >= (int)src->trees.size())
+    return fail(TTNS_EINVAL, "ttns_copy_state: bad arguments");
+  TreeState& td = dst->trees[dtree];
+  TreeState& ts = src->trees[stree];
+  if (td.n != ts.n || td.ht.parent != ts.ht.parent)
+    return fail(TTNS_EINVAL, "ttns_copy_state: the trees differ");
+  for (int v = 0; v < td.n; ++v)
+    for (int a = 0; a < kMaxRank; ++a)
+      if (td.shape[v].dims[a] != ts.shape[v].dims[a])
+        return fail(TTNS_EINVAL, "ttns_copy_state: node " + std::to_string(v) + " has another shape");
+  int rc = recentre(*src);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(src->stream));
+  for (int v = 0; v < td.n; ++v)
+    HIPCHK(hipMemcpyAsync(td.T[v], ts.T[v], (size_t)td.shape[v].size * sizeof(cd), hipMemcpyDeviceToDevice,
+                          dst->stream));
+  std::vector<Op> ops;
+  Builder b{*dst, td, dtree, ops};
+  for (int v = td.n - 1; v > 0; --v) b.env_update(v, parent_of(td, v));
+  if ((rc = validate_program(*dst, ops, false))) return rc;
+  if ((rc = run_ops(*dst, ops))) return rc;
+  td.centre = 0;
+  HIPCHK(hipStreamSynchronize(dst->stream));
+  return TTNS_OK;
+}
+
 // Entry points on a context: the message of a failure is kept on the
 // context as well as for the calling thread.
 #define TTNS_CTX_CALL(c, expr)            \
@@ -2328,6 +2397,13 @@ int ttns_observe(ttns_ctx* c, int32_t kind, int32_t tree, int32_t index, double*
   TTNS_CTX_CALL(c, ttns_observe_impl(c, kind, tree, index, host_out, n_out));
 }
 int ttns_profile(ttns_ctx* c, int32_t enable) { TTNS_CTX_CALL(c, ttns_profile_impl(c, enable)); }
+int ttns_energy_surfaces(ttns_ctx* c, int32_t tree, double rank_tol, int32_t* n_bath, double* host_values,
+                         double* host_matrix, size_t cap) {
+  TTNS_CTX_CALL(c, ttns_energy_surfaces_impl(c, tree, rank_tol, n_bath, host_values, host_matrix, cap));
+}
+int ttns_copy_state(ttns_ctx* dst, int32_t dst_tree, ttns_ctx* src, int32_t src_tree) {
+  TTNS_CTX_CALL(dst, ttns_copy_state_impl(dst, dst_tree, src, src_tree));
+}
 int ttns_profile_read(ttns_ctx* c, int32_t reset, double* avg_ms, int64_t* launches, double* flops) {
   TTNS_CTX_CALL(c, ttns_profile_read_impl(c, reset, avg_ms, launches, flops));
 }

@@ -45,7 +45,7 @@ int add_node(HostTree& t, int parent, int d, int D, const std::vector<cd>& loc) 
 }
 
 struct BosonOps {
-  int b, bd, num, x;
+  int b, bd, num, x, p, p2;  // p = i (b^+ - b) / sqrt(2), p2 = p p
 };
 
 BosonOps boson_ops(HostTree& t, int d, std::map<int, BosonOps>& cache) {
@@ -61,7 +61,27 @@ BosonOps boson_ops(HostTree& t, int d, std::map<int, BosonOps>& cache) {
     x[k * d + (k - 1)] = cd{v, 0};
   }
   for (int k = 0; k < d; ++k) num[k * d + k] = cd{(double)k, 0};
-  BosonOps o{add_op(t, b, d), add_op(t, bd, d), add_op(t, num, d), add_op(t, x, d)};
+  // momentum p = i (b^+ - b) / sqrt(2) and its square (matrix product in the
+  // truncated space)
+  std::vector<cd> pm(d * d, cd{0, 0}), p2(d * d, cd{0, 0});
+  const double r2 = 1.0 / std::sqrt(2.0);
+  for (int r = 0; r < d; ++r)
+    for (int c = 0; c < d; ++c) {
+      const double v = bd[r * d + c].x - b[r * d + c].x;  // real
+      pm[r * d + c] = cd{0.0, v * r2};
+    }
+  for (int r = 0; r < d; ++r)
+    for (int c = 0; c < d; ++c) {
+      double re = 0.0, im = 0.0;
+      for (int k = 0; k < d; ++k) {
+        const cd a = pm[r * d + k], e = pm[k * d + c];
+        re += a.x * e.x - a.y * e.y;
+        im += a.x * e.y + a.y * e.x;
+      }
+      p2[r * d + c] = cd{re, im};
+    }
+  BosonOps o{add_op(t, b, d), add_op(t, bd, d), add_op(t, num, d), add_op(t, x, d), add_op(t, pm, d),
+             add_op(t, p2, d)};
   cache[d] = o;
   return o;
 }
@@ -131,6 +151,13 @@ bool star_to_tree(const ttns_star_model& m, HostTree& t, std::string& err) {
     for (int k = 0; k + 1 < L; ++k) {
       t.terms.push_back(HostTerm{nodes[k], bo.bd, nodes[k + 1], bo.b, hop[k]});
       t.terms.push_back(HostTerm{nodes[k], bo.b, nodes[k + 1], bo.bd, hop[k]});
+    }
+    if (m.potential) {
+      // H - T: T = sum over the chain's modes of (w/2) P^2 = (1/2) p^T M p
+      // with M the chain's tridiagonal matrix (eps on the diagonal, hop
+      // beside it) and p the site momenta
+      for (int k = 0; k < L; ++k) t.terms.push_back(HostTerm{nodes[k], bo.p2, -1, -1, -0.5 * eps[k]});
+      for (int k = 0; k + 1 < L; ++k) t.terms.push_back(HostTerm{nodes[k], bo.p, nodes[k + 1], bo.p, -hop[k]});
     }
     t.obs_node.push_back(head);
     t.obs_op.push_back(bo.num);

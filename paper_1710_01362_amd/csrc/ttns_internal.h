@@ -249,6 +249,18 @@ hipError_t launch_persistent(const Op* dev_ops, const int* dev_begin,
                              const DevTables& t, hipStream_t s);
 hipError_t launch_set_half_step(double* dst, double h, hipStream_t s);
 
+// surfaces.hip: dense kernels of the energy surfaces and bond entropy
+int surf_eig_max();
+hipError_t launch_herm_eig(const cd* A, int N, int lda, double* evals, cd* vecs, int graded, hipStream_t s);
+hipError_t launch_bath_vectors(const cd* X, int ldx, int nel, int nb, const cd* W, const double* lam, int r,
+                               int normalise, cd* B, int ldb, hipStream_t s);
+hipError_t launch_surf_fill(cd* X, const cd* B, int ldb, int k, int l, int nel, int nb, hipStream_t s);
+hipError_t launch_surf_dots(const cd* B, int ldb, const cd* Y, int ldy, int nel, int nb, int r, cd* part, int nvb,
+                            hipStream_t s);
+hipError_t launch_surf_fold(const cd* part, int nvb, int cnt, cd* M, int ldm, int col, hipStream_t s);
+hipError_t launch_gram(const cd* R, int D, cd* G, hipStream_t s);
+hipError_t launch_entropy(const double* lam, int N, double* out, hipStream_t s);
+
 // MFMA limits: largest bond dimension per precision
 int mode_max_bond(int prec);
 // padded real operand size (2D rounded up to the MFMA K granule) of a group

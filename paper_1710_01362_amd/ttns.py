@@ -34,7 +34,8 @@ EXPORTED = [
     "ttns_default_opts", "ttns_ohmic_chain", "ttns_workspace_size", "ttns_star_workspace_size",
     "ttns_build", "ttns_star_build", "ttns_apply_heff", "ttns_tdvp_step", "ttns_observe",
     "ttns_profile", "ttns_profile_read", "ttns_profile_kernel", "ttns_tuning_report", "ttns_destroy",
-    "ttns_last_error", "ttns_star_build_noalloc", "ttns_struct_sizes",
+    "ttns_last_error", "ttns_star_build_noalloc", "ttns_struct_sizes", "ttns_energy_surfaces",
+    "ttns_copy_state",
 ]
 # kernel ids (include/ttns.h) -> device symbol
 KERNELS = {0: "ttns::k_op<0> (scalar apply)", 1: "ttns::k_op<1> (scalar H_eff + Lanczos dots)",
@@ -73,7 +74,7 @@ class StarModel(C.Structure):
                 ("s", C.POINTER(C.c_double)), ("length", C.POINTER(C.c_int32)),
                 ("local_dim", C.POINTER(C.c_int32)), ("bond_dim", C.POINTER(C.c_int32)),
                 ("topology", C.c_int32), ("er_bond_dim", C.c_int32),
-                ("obb_dim", C.POINTER(C.c_int32))]
+                ("obb_dim", C.POINTER(C.c_int32)), ("potential", C.c_int32)]
 
 
 class Opts(C.Structure):
@@ -122,6 +123,8 @@ def lib():
             if name not in ("ttns_default_opts", "ttns_last_error"):
                 getattr(L, name).restype = C.c_int
         L.ttns_struct_sizes.argtypes = [C.POINTER(S), I]
+        L.ttns_energy_surfaces.argtypes = [P, I, D, C.POINTER(I), C.POINTER(D), C.POINTER(D), S]
+        L.ttns_copy_state.argtypes = [P, I, P, I]
         _check_struct_sizes(L)
         _lib = L
     return _lib
@@ -208,6 +211,7 @@ def star_model(m, keep):
     sm.topology = 1 if m["topology"] == "er" else 0
     sm.er_bond_dim = int(m.get("er_D", ch[0]["D"] if ch else 1))
     sm.obb_dim = bufs["obb"]
+    sm.potential = 1 if m.get("potential") else 0
     return sm
 
 
@@ -352,6 +356,30 @@ class Context:
     def entropy(self, tree, node):
         """Entanglement entropy across the bond (node, parent(node))."""
         return float(self.ttns_observe(OBS_ENTROPY, tree, node, n=1)[0])
+
+    def energy_surfaces(self, tree=0, rank_tol=1e-5, matrix=False):
+        """Eigenvalues (ascending) of the effective matrix of this context's
+        operator between (bath Schmidt state, electronic state) products;
+        with matrix=True also the matrix ((r n) x (r n) complex)."""
+        n = int(round(np.sqrt((int(self.ttns_observe(OBS_RECORD_SIZE, tree, n=1)[0]) - 2) / 2)))
+        while 2 * n * n + 2 > int(self.ttns_observe(OBS_RECORD_SIZE, tree, n=1)[0]):
+            n -= 1
+        vals = np.zeros(n * n)
+        mat = np.zeros(2 * n ** 4) if matrix else None
+        r = C.c_int32()
+        check(lib().ttns_energy_surfaces(self.ctx, int(tree), float(rank_tol), C.byref(r),
+                                         vals.ctypes.data_as(C.POINTER(C.c_double)),
+                                         mat.ctypes.data_as(C.POINTER(C.c_double)) if matrix else None,
+                                         C.c_size_t(vals.size)))
+        N = r.value * n
+        if not matrix:
+            return vals[:N]
+        M = mat[:2 * N * N].reshape(N, N, 2)
+        return vals[:N], M[..., 0] + 1j * M[..., 1]
+
+    def copy_state_from(self, src, tree=0, src_tree=0):
+        """This context's tree takes src's state (ttns_copy_state)."""
+        check(lib().ttns_copy_state(self.ctx, int(tree), src.ctx, int(src_tree)))
 
     def bond_dims(self, tree, n_nodes):
         return self.ttns_observe(OBS_BOND_DIMS, tree, n=n_nodes).astype(int)
